@@ -1,0 +1,239 @@
+"""Benchmark of the deep-copy + pointer-chain kernel hot path on one MI355X.
+
+Default workload (the Linear chain of the paper's Section 4.1 at its largest
+single-structure size): 8 nested nodes, only the last one owning an FP64
+payload of 2^24 elements; a step is
+
+    attach (device relocation of every pointer)          -- Figure 2 (d)
+    100 passes of x = fma(x, 1.0001, 0.5), address resolved once
+                                                      -- pointerchain, Sec. 3
+    100 passes of the same with the chain walked on every element access
+    detach (demarshalling: pointers back to host values)
+
+with the marshalled image already resident in HBM when the timed region
+starts. `value` is the algorithmic bytes of a step over its time. The
+host-link part of the deep copy (pack + host-to-device + copy back) is timed
+separately and reported as `host_link` / `end_to_end`, never as `value`.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload linear|wide|batched|served]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E
+LINK_PEAK_GBPS = 63.0       # PCIe Gen5 x16 per direction after encoding (32 GT/s x16 on the box)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="linear", choices=["linear", "wide", "batched", "served"])
+    ap.add_argument("--passes", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-link", action="store_true", help="skip the host-link measurements")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=float), q))
+
+
+def link_peak(torch):
+    """Pinned 1 GiB copies in each direction (the host link's achievable peak)."""
+    n = 1 << 30
+    h = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(n, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    out = {}
+    for name, fn in (("h2d", lambda: d.copy_(h, non_blocking=True)), ("d2h", lambda: h.copy_(d, non_blocking=True))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(3):
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        out[name] = n / min(ts) / 1e9
+    del h, d
+    return out
+
+
+def cpu_baseline_linear(args, passes):
+    """The CPU oracle on the same workload, bounded: deep copy, `passes` fma
+    passes per mode (the oracle has one result for both modes, so it runs
+    once per mode), copy back. Single-threaded."""
+    import fixtures as fx
+    import oracle as orc
+    t = fx.linear()
+    chain = [(1, 0)] * 7 + [(0, 0)]
+    leaf = 8 << 24
+    t0 = time.perf_counter()
+    c = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 1 << 40)
+    t1 = time.perf_counter()
+    c.run_kernel(1.0001, 0.5, iters=passes, select="chain", chain=chain)
+    c.run_kernel(1.0001, 0.5, iters=passes, select="chain", chain=chain)
+    t2 = time.perf_counter()
+    c.copy_back()
+    t3 = time.perf_counter()
+    kernel_bytes = 2 * 2 * leaf * passes
+    return {"value": round(kernel_bytes / (t2 - t1) / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"linear chain k=8, 2^24 FP64: deep copy, {passes} fma passes x 2 modes, copy back; "
+                      f"kernel GB/s over the passes (deep copy {t1 - t0:.3f} s, copy back {t3 - t2:.3f} s)",
+            "seconds": round(t3 - t0, 3)}
+
+
+def bench_linear(args, torch, dc):
+    import fixtures as fx
+    t = fx.linear()
+    ctx = dc.Context(0)
+    schema = dc.Schema(t.types)
+    plan = dc.Plan(schema, t.root_type, t.roots)
+    info = plan.info()
+    arena = torch.empty(plan.arena_bytes, dtype=torch.uint8, device="cuda")
+    scratch = torch.empty(plan.scratch_bytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    chain = [(1, 0)] * 7 + [(0, 0)]
+    leaf = info.leaf_bytes
+    P = args.passes
+
+    tree = dc.Tree(ctx, plan, arena, scratch)  # pack + H2D + attach
+    tree.resolve_chain(chain)
+    tree.detach()  # the marshalled image, host pointers in it, resident in HBM
+    torch.cuda.synchronize()
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def step(rec):
+        e = [ev() for _ in range(6)]
+        e[0].record(s)
+        tree.attach()
+        e[1].record(s)
+        tree.run_kernel(mode="resolved", select="chain", chain=chain, iters=P, a=1.0001, b=0.5)
+        e[2].record(s)
+        tree.run_kernel(mode="deref_each", select="chain", chain=chain, iters=P, a=1.0001, b=0.5)
+        e[3].record(s)
+        tree.detach()
+        e[4].record(s)
+        rec.append(e)
+
+    for _ in range(args.warmup):
+        step([])
+    torch.cuda.synchronize()
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_s = [r[0].elapsed_time(r[4]) / 1e3 for r in recs]
+    attach_s = [r[0].elapsed_time(r[1]) / 1e3 for r in recs]
+    res_s = [r[1].elapsed_time(r[2]) / 1e3 for r in recs]
+    der_s = [r[2].elapsed_time(r[3]) / 1e3 for r in recs]
+    detach_s = [r[3].elapsed_time(r[4]) / 1e3 for r in recs]
+    tree.check()
+
+    reloc_bytes = info.nslots_nonnull * 16 + info.nslots * 8 + info.nobjects * 16
+    kernel_bytes = 2 * leaf * P
+    step_bytes = 2 * kernel_bytes + 2 * reloc_bytes
+    dev_time = sum(step_s)
+    value = step_bytes * len(step_s) / dev_time / 1e9
+    res_gbps = 2 * leaf / (sum(res_s) / len(res_s) / P) / 1e9
+    der_gbps = 2 * leaf / (sum(der_s) / len(der_s) / P) / 1e9
+    dominant = "deref_each" if sum(der_s) > sum(res_s) else "resolved"
+    dom_t = (sum(der_s) if dominant == "deref_each" else sum(res_s)) / len(step_s) / P
+    achieved = 2 * leaf / dom_t / 1e9
+    out = {
+        "metric": "deep-copy+kernel effective GB/s vs HBM/link roofline; p50/p99 latency",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dev_time / len(step_s), 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"linear chain: 8 nested structs, LLinit, FP64 leaf of 2^24 elements, "
+                               f"{P} fma passes resolved + {P} per-access deref, attach/detach on device",
+                   "k": 8, "n": 1 << 24, "passes": P, "leaf_bytes": leaf, "arena_bytes": plan.arena_bytes},
+        "roofline": {"bound": "hbm", "kernel": f"k_stream_{'deref' if dominant == 'deref_each' else 'resolved'}",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "bytes_per_launch": 2 * leaf, "avg_launch_us": round(dom_t * 1e6, 3)},
+        "latency_ms": {"p50": round(1e3 * pct(step_s, 50), 4), "p99": round(1e3 * pct(step_s, 99), 4)},
+        "modes": {"resolved_GBps": round(res_gbps, 1), "deref_each_GBps": round(der_gbps, 1),
+                  "deref_over_resolved_time": round(sum(der_s) / sum(res_s), 3),
+                  "attach_us": round(1e6 * pct(attach_s, 50), 2), "detach_us": round(1e6 * pct(detach_s, 50), 2)},
+        "wall_s": round(wall, 3),
+    }
+
+    if not args.no_link:
+        # the host-link part: pack + host-to-device + relocation, then copy back
+        h2d, d2h, e2e = [], [], []
+        peak = link_peak(torch)
+        for r in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tr = dc.Tree(ctx, plan, arena, scratch)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            tr.run_kernel(mode="resolved", select="chain", chain=chain, iters=P, a=1.0001, b=0.5)
+            tr.run_kernel(mode="deref_each", select="chain", chain=chain, iters=P, a=1.0001, b=0.5)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            tr.copy_back()
+            t3 = time.perf_counter()
+            tr.release()
+            h2d.append(plan.arena_bytes / (t1 - t0) / 1e9)
+            d2h.append(leaf / (t3 - t2) / 1e9)
+            e2e.append(t3 - t0)
+        out["host_link"] = {"h2d_GBps": round(max(h2d), 2), "d2h_GBps": round(max(d2h), 2),
+                            "pinned_peak_h2d_GBps": round(peak["h2d"], 2), "pinned_peak_d2h_GBps": round(peak["d2h"], 2),
+                            "spec_peak_GBps": LINK_PEAK_GBPS,
+                            "h2d_frac_of_spec": round(max(h2d) / LINK_PEAK_GBPS, 4),
+                            "d2h_frac_of_spec": round(max(d2h) / LINK_PEAK_GBPS, 4)}
+        job_bytes = plan.arena_bytes + leaf + 2 * kernel_bytes
+        out["end_to_end"] = {"what": "pack + H2D + attach + both kernels + copy back, host buffers in and out",
+                             "GBps": round(job_bytes / min(e2e) / 1e9, 2),
+                             "p50_ms": round(1e3 * pct(e2e, 50), 3), "p99_ms": round(1e3 * pct(e2e, 99), 3)}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
+              f"Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1906_01128_amd import dc
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    log(args, f"libdc {dc.version()} on {torch.cuda.get_device_name(0)}")
+    if args.workload == "linear":
+        out = bench_linear(args, torch, dc)
+    else:
+        import bench_extra
+        out = bench_extra.run(args, torch, dc)
+    if not args.no_cpu_baseline and args.workload == "linear":
+        log(args, "cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline_linear(args, passes=args.passes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

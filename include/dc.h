@@ -1,0 +1,348 @@
+/* dc.h -- deep copy of pointer-linked struct trees into one MI355X device
+ * arena, device-side pointer relocation, pointer-chain resolution and leaf
+ * kernels. C ABI: plain pointers and sizes, no C++ or torch types.
+ *
+ * The operations follow the paper's problem statement:
+ *   - describing nested structures (Section 2: structs whose members point to
+ *     arrays of primitives or of other structs; the Linear node of
+ *     Section 4.1 with its count members nA and nLnext);
+ *   - the deep copy (Section 2, Figure 2 steps a-d: initialise, copy the main
+ *     structure, copy the nested ones, fix the pointers on the device), done
+ *     as marshalling into one contiguous buffer (Algorithm 1: size the tree,
+ *     allocate once, hand out space in request order, transfer the buffer in
+ *     one batch, then attach every pointer on the device);
+ *   - resolving a pointer chain once to its effective address (Section 3);
+ *   - running the kernel once and transferring the tree back (Algorithm 2,
+ *     steps 4 and 5; the scaling kernel of Sections 4.1.2 and 4.2.2).
+ *
+ * Conventions for every call:
+ *   - Returns dc_status: DC_OK (0) or a negative DC_E_* code. The text of the
+ *     last error of the calling thread is returned by dc_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - A "stream" is a hipStream_t passed as void*; NULL means the null stream.
+ *   - "device pointer" arguments are HIP device allocations on the context's
+ *     device; "host pointer" arguments are ordinary host memory.
+ *   - On error, every output handle is set to NULL and nothing is leaked;
+ *     device buffers written before the error hold unspecified bytes.
+ *   - One context, and everything made from it, is used by one host thread
+ *     at a time. A server (dc_server_*) owns its own threads.
+ */
+#ifndef DC_H
+#define DC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dc_status;
+enum {
+  DC_OK = 0,
+  DC_E_INVAL = -1,    /* null/unknown handle, bad argument, unknown type, negative count */
+  DC_E_RANGE = -2,    /* buffer too small, pointer into the middle of an array, chain past a null */
+  DC_E_CONFLICT = -3, /* one address reached again as a different kind, type or length */
+  DC_E_NOMEM = -4,    /* host or pinned allocation failed */
+  DC_E_HIP = -5,      /* a HIP runtime call failed (text names it) */
+  DC_E_STATE = -6,    /* call out of order, released tree, device-side check failed */
+  DC_E_BUDGET = -7    /* a served job can never fit the device-memory budget */
+};
+
+/* element kinds of an array a pointer member refers to */
+typedef enum { DC_KIND_STRUCT = 0, DC_KIND_F32 = 1, DC_KIND_F64 = 2, DC_KIND_I32 = 3, DC_KIND_I64 = 4, DC_KIND_U8 = 5 } dc_kind;
+
+typedef struct dc_ctx_s* dc_ctx;
+typedef struct dc_schema_s* dc_schema;
+typedef struct dc_plan_s* dc_plan;
+typedef struct dc_tree_s* dc_tree;
+typedef struct dc_graph_s* dc_graph;
+typedef struct dc_server_s* dc_server;
+
+/* One pointer member of a struct type. The member holds the address of an
+ * array of `count` elements of `kind` (of struct type `type_id` when kind is
+ * DC_KIND_STRUCT), or NULL for no array. The count is read from a signed
+ * integer member of the same struct element (count_offset >= 0, count_bytes
+ * 4 or 8) times count_mult (e.g. 3 for an array of double3), or is
+ * fixed_count when count_offset == -1. offset must be a multiple of 8. */
+typedef struct {
+  uint32_t offset;
+  uint32_t kind;
+  uint32_t type_id;
+  int32_t count_offset;
+  uint32_t count_bytes;
+  uint32_t count_mult;
+  uint64_t fixed_count;
+} dc_field;
+
+/* One step of a pointer chain: read pointer member `field` (its position in
+ * the field list given to dc_schema_describe) of the current struct element;
+ * unless this is the last step, continue at element `index` of the array it
+ * points to. */
+typedef struct {
+  uint32_t field;
+  uint32_t reserved;
+  uint64_t index;
+} dc_step;
+
+/* A resolved chain: the device address of the array at the end of the chain,
+ * its element count and kind. */
+typedef struct {
+  uint64_t dev_addr;
+  uint64_t count;
+  uint32_t kind;
+  uint32_t reserved;
+} dc_chain;
+
+/* A placed object: where an array of the host tree lives in the arena. */
+typedef struct {
+  uint64_t host_addr;
+  uint64_t offset;
+  uint64_t bytes;
+  uint64_t count;
+  uint32_t kind;
+  uint32_t type_id;
+} dc_object;
+
+typedef struct {
+  uint64_t nobjects;      /* arrays placed in the arena */
+  uint64_t nslots;        /* pointer members of all struct elements (null or not) */
+  uint64_t nslots_nonnull;
+  uint64_t nleaves;       /* FP32/FP64 arrays with at least one element */
+  uint64_t payload_bytes; /* sum of object bytes, no padding */
+  uint64_t leaf_bytes;    /* sum of FP32/FP64 array bytes */
+  uint64_t arena_bytes;   /* device arena size the plan needs */
+  uint64_t scratch_bytes; /* device scratch size the plan needs */
+  uint64_t out_bytes;     /* out-of-place leaf image size (see dc_kernel_args) */
+  uint64_t nsegments;     /* relocation work units */
+  uint64_t nroots;
+} dc_plan_info;
+
+/* ---- lifecycle --------------------------------------------------------------- */
+
+/* A context on HIP device `device`: owns pinned host staging buffers and a
+ * pool of host threads for packing. */
+dc_status dc_ctx_create(int device, dc_ctx* out);
+dc_status dc_ctx_destroy(dc_ctx ctx);
+
+dc_status dc_schema_create(dc_schema* out);
+dc_status dc_schema_destroy(dc_schema schema);
+
+/* Registers a struct type of `size` bytes and alignment `align` with its
+ * pointer members (Section 2: the nested, user-defined members that must be
+ * followed; non-pointer members are copied as plain bytes). Type ids are
+ * assigned 0, 1, 2, ... in call order; a field may name a type id that is
+ * described later. At most 16 pointer fields per type and 64 types.
+ * DC_E_INVAL for misaligned or overlapping pointer members, count members
+ * outside the struct, or bad kinds. */
+dc_status dc_schema_describe(dc_schema schema, const char* name, uint32_t size, uint32_t align,
+                             const dc_field* fields, uint32_t nfields, uint32_t* out_type_id);
+
+/* ---- deep copy (Section 2, Figure 2; Algorithm 1) ------------------------------ */
+
+/* Plans the deep copy of the trees under roots[0..nroots): each root is the
+ * host address of one struct of type root_type. The host tree is walked
+ * depth-first in pre-order (elements in index order, pointer members in
+ * ascending offset order; an address reached again is not visited again),
+ * and every array gets an arena offset: the first at 0, each next one at the
+ * next multiple of `align` at or after the previous one's end (a zero-length
+ * array occupies one byte). align: power of two, 16..4096 (64 if 0).
+ * ctx may be NULL (planning needs no device).
+ * The plan reads the host tree; the tree's shape (pointers and counts) must
+ * not change while the plan is used. Values may change.
+ * Errors: DC_E_INVAL (null root, negative count, unknown type),
+ * DC_E_CONFLICT (an address reached as two different arrays), DC_E_RANGE
+ * (a pointer into the middle of another array). */
+dc_status dc_plan_create(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* const* roots, uint64_t nroots,
+                         uint64_t align, dc_plan* out, uint64_t* arena_bytes, uint64_t* scratch_bytes);
+dc_status dc_plan_destroy(dc_plan plan);
+dc_status dc_plan_query(dc_plan plan, dc_plan_info* out);
+/* Copies up to cap placed objects, in arena order, into out; *n receives the
+ * total number of objects. */
+dc_status dc_plan_objects(dc_plan plan, dc_object* out, uint64_t cap, uint64_t* n);
+
+/* The deep copy: packs the host tree into pinned staging in arena order
+ * (padding zeroed), transfers it to d_arena over the host link in pipelined
+ * chunks, uploads the plan's relocation tables into d_scratch and relocates
+ * every pointer member on the device (host address -> d_arena + offset; null
+ * stays null). Returns once the host tree has been read; the transfer and the
+ * relocation may still be running on `stream`.
+ * d_arena (>= arena_bytes) and d_scratch (>= scratch_bytes) are device
+ * buffers owned by the caller, 256-byte aligned, that must outlive the tree.
+ * Errors: DC_E_RANGE (buffers too small or misaligned), DC_E_HIP. */
+dc_status dc_deep_copy_to_device(dc_ctx ctx, dc_plan plan, void* d_arena, uint64_t arena_bytes, void* d_scratch,
+                                 uint64_t scratch_bytes, void* stream, dc_tree* out);
+
+/* Like dc_deep_copy_to_device but without the relocation: the arena holds
+ * the host bytes verbatim (host addresses in every pointer member) until
+ * dc_attach or dc_batch_run relocates it. */
+dc_status dc_stage_to_device(dc_ctx ctx, dc_plan plan, void* d_arena, uint64_t arena_bytes, void* d_scratch,
+                             uint64_t scratch_bytes, void* stream, dc_tree* out);
+
+/* Device pointer passes over every pointer member of the arena (Algorithm 1's
+ * attach of each pointer; the reverse, detach, is part of demarshalling):
+ * attach rewrites host addresses to device addresses, detach rewrites device
+ * addresses back to the host addresses they came from. The tree must be in
+ * the opposite state (DC_E_STATE otherwise). Asynchronous on `stream`; an
+ * address that is not a planned array start is counted in a device error
+ * flag that the next synchronous call reports as DC_E_STATE. */
+dc_status dc_attach(dc_tree tree, void* stream);
+dc_status dc_detach(dc_tree tree, void* stream);
+
+/* ---- pointerchain (Section 3) ---------------------------------------------------- */
+
+/* Resolves a chain once, on the device, by following the relocated pointers
+ * of root `root_index`; checks the result against the plan. Synchronous.
+ * Errors: DC_E_INVAL (bad field or steps), DC_E_RANGE (null before the last
+ * step, index past the array), DC_E_STATE (not attached). */
+dc_status dc_resolve_chain(dc_tree tree, uint64_t root_index, const dc_step* steps, uint32_t nsteps, void* stream,
+                           dc_chain* out);
+
+/* ---- leaf kernels (Algorithm 2 step 4) --------------------------------------------- */
+
+enum { DC_MODE_RESOLVED = 0, DC_MODE_DEREF_EACH = 1 };
+enum { DC_SELECT_CHAIN = 0, DC_SELECT_ALL_LEAVES = 1 };
+
+/* x <- fma(x, a, b) for every element of the selected leaves, `iters` full
+ * passes (each pass a separate sweep over the data). FP64 leaves use a and b
+ * in binary64, FP32 leaves use af and bf in binary32; both are single
+ * correctly rounded fused multiply-adds.
+ * select CHAIN: the FP32/FP64 array at the end of `chain` from root
+ * root_index; ALL_LEAVES: every FP32/FP64 array of the tree.
+ * mode RESOLVED: the array address is resolved once (Section 3) and the kernel
+ * indexes it directly. DEREF_EACH: every element access walks the whole chain
+ * from the root again, reading each pointer from the arena (the paper's
+ * per-iteration dereference); for ALL_LEAVES the chain of a leaf is the path
+ * by which the walk first reached it.
+ * d_out NULL: in place. Otherwise a device buffer of at least out_bytes that
+ * receives the results as a leaf image: the selected leaves in arena order,
+ * each at the next multiple of the plan alignment after the previous one's
+ * end, the first at 0; the arena is left unchanged.
+ * Asynchronous on `stream`. */
+typedef struct {
+  uint32_t mode;
+  uint32_t select;
+  uint32_t iters;
+  uint32_t nsteps;
+  double a, b;
+  float af, bf;
+  uint64_t root_index;
+  const dc_step* chain;
+  void* d_out;
+  uint64_t out_bytes;
+} dc_kernel_args;
+
+dc_status dc_run_kernel(dc_tree tree, const dc_kernel_args* args, void* stream);
+
+/* Bytes of the out-of-place leaf image for args (select and chain). */
+dc_status dc_out_bytes(dc_tree tree, const dc_kernel_args* args, uint64_t* out);
+
+/* ---- copy back (Algorithm 2 step 5) ------------------------------------------------ */
+
+enum { DC_COPY_LEAVES = 1, DC_COPY_SCALARS = 2 };
+/* Transfers the arena back and writes into the host tree: LEAVES = every
+ * primitive array; SCALARS = the non-pointer bytes of every struct element.
+ * Host pointer members are never written. Returns when the host tree is
+ * updated (waits for earlier work on `stream`). */
+dc_status dc_copy_back(dc_tree tree, uint32_t flags, void* stream);
+
+/* Releases the tree's host-side state (not the caller's device buffers). */
+dc_status dc_tree_release(dc_tree tree);
+/* Waits for `stream`, then reports a device-side error recorded by earlier
+ * passes of this tree (DC_E_STATE) or DC_OK. */
+dc_status dc_tree_check(dc_tree tree, void* stream);
+
+/* ---- batched form: one persistent launch ------------------------------------------ */
+
+/* Tile shapes of the persistent relocate+compute kernel. Zero fields take
+ * the tuned or default choice. */
+typedef struct {
+  uint32_t block;          /* threads per workgroup: 256, 512 or 1024 */
+  uint32_t wg_per_cu;      /* resident workgroups per compute unit */
+  uint32_t tile_chunks;    /* 16-byte chunks per compute tile */
+  uint32_t reserved;
+} dc_tune;
+
+enum { DC_BATCH_ATTACH = 1, DC_BATCH_DETACH = 2 };
+/* Every structure's relocation and its leaves' kernel (args: RESOLVED,
+ * ALL_LEAVES, iters == 1) in one persistent launch: workgroups take
+ * relocation units, then compute tiles, then (DETACH) reverse relocation
+ * units from one device work queue. ATTACH requires a staged (unrelocated)
+ * tree; DETACH leaves it staged again. tune NULL: the cached autotuner choice
+ * or defaults. Asynchronous on `stream`. */
+dc_status dc_batch_run(dc_tree tree, const dc_kernel_args* args, const dc_tune* tune, uint32_t flags, void* stream);
+
+/* Times candidate tile shapes of dc_batch_run with ATTACH|DETACH on this
+ * tree (which leaves its leaf values changed: deep copy again before a run
+ * whose values matter) and returns the fastest; the choice is cached on disk
+ * keyed by device and workload shape (DC_TUNE_CACHE, default
+ * ~/.cache/dc_tune.json). */
+dc_status dc_autotune(dc_tree tree, const dc_kernel_args* args, uint32_t reps, dc_tune* out);
+
+/* Captures dc_batch_run(tree, args, tune, flags) into a HIP graph; optionally
+ * preceded by the host-to-device transfer of the staged image (upload != 0,
+ * which keeps a pinned copy of the whole image) and followed by the transfer
+ * back of the arena into pinned memory (download != 0). */
+dc_status dc_graph_create(dc_tree tree, const dc_kernel_args* args, const dc_tune* tune, uint32_t flags,
+                          int upload, int download, dc_graph* out);
+dc_status dc_graph_launch(dc_graph graph, void* stream);
+dc_status dc_graph_destroy(dc_graph graph);
+
+/* ---- served form ---------------------------------------------------------------- */
+
+/* A server admits deep-copy+kernel jobs against a device-memory budget,
+ * keeps copied structures resident for reuse, overlaps the transfers and
+ * kernels of several jobs, and batches the kernels of ready jobs. */
+typedef struct {
+  uint64_t budget_bytes;   /* device bytes for arenas, scratch and outputs */
+  uint32_t max_inflight;   /* jobs on the device at once */
+  uint32_t nstreams;       /* copy/compute streams */
+  uint64_t align;          /* arena alignment (0: 64) */
+} dc_server_config;
+
+typedef struct {
+  uint32_t root_type;
+  uint32_t reserved;
+  const void* root;        /* host address of the structure's root struct */
+  uint64_t key;            /* identity for residency: equal keys name the same
+                              unchanged structure; 0 = never reuse */
+  double a, b;             /* the job's kernel: out = fma(leaf, a, b) */
+  float af, bf;
+  void* out_host;          /* host buffer receiving the leaf image */
+  uint64_t out_bytes;      /* its size; must be >= the structure's leaf image */
+} dc_request;
+
+typedef struct {
+  uint64_t id;
+  dc_status status;
+  uint32_t reused;         /* 1 if the structure was already resident */
+  double t_submit, t_admit, t_done; /* seconds, steady clock */
+  uint64_t out_bytes;
+} dc_result;
+
+typedef struct {
+  uint64_t submitted, completed, reused, evictions, batches;
+  uint64_t h2d_bytes, d2h_bytes, kernel_bytes;
+  uint64_t resident_bytes, peak_bytes;
+} dc_server_stats;
+
+dc_status dc_server_create(dc_ctx ctx, dc_schema schema, const dc_server_config* cfg, dc_server* out);
+/* Queues a job (the structure is read when the job is admitted, so it must
+ * stay unchanged until its result arrives); returns its id. DC_E_BUDGET if
+ * it can never fit the budget. */
+dc_status dc_server_submit(dc_server srv, const dc_request* req, uint64_t* id);
+/* Waits for job `id` (timeout_s < 0: forever) and returns its result. */
+dc_status dc_server_wait(dc_server srv, uint64_t id, double timeout_s, dc_result* out);
+dc_status dc_server_stats_get(dc_server srv, dc_server_stats* out);
+dc_status dc_server_destroy(dc_server srv);
+
+/* ---- misc ------------------------------------------------------------------------ */
+
+const char* dc_last_error(void);
+/* Library version string. */
+const char* dc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

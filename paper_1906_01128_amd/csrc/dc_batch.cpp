@@ -1,0 +1,290 @@
+// libdc batched form: one persistent relocate+compute launch over every
+// structure of a plan, its capture in a HIP graph, and the tile autotuner.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <sys/stat.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "dc_host.h"
+
+namespace dc {
+
+static const dc_tune kDefaultTune = {256, 4, 1024, 0};
+
+static dc_status check_tune(const dc_tune& t) {
+  if (t.block != 256 && t.block != 512 && t.block != 1024) return fail(DC_E_INVAL, "tune.block %u", t.block);
+  if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return fail(DC_E_INVAL, "tune.wg_per_cu %u", t.wg_per_cu);
+  if (t.tile_chunks < kMinTileChunks || t.tile_chunks > kMaxTileChunks || (t.tile_chunks & (t.tile_chunks - 1)))
+    return fail(DC_E_INVAL, "tune.tile_chunks %u", t.tile_chunks);
+  const uint32_t u = t.tile_chunks / t.block;
+  if (t.tile_chunks % t.block || (u != 1 && u != 2 && u != 4 && u != 8))
+    return fail(DC_E_INVAL, "tune.tile_chunks / tune.block must be 1, 2, 4 or 8");
+  return DC_OK;
+}
+
+// ---- tuning cache: one JSON object per line -----------------------------------------------
+
+static std::string cache_path() {
+  const char* p = getenv("DC_TUNE_CACHE");
+  if (p && *p) return p;
+  const char* home = getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.cache/dc_tune.json";
+}
+
+// workload shape: coarse buckets so that similar trees share a choice
+static std::string tune_key(dc_tree t) {
+  dc_plan p = t->plan;
+  auto bucket = [](uint64_t x) {
+    int b = 0;
+    while (x > 1) {
+      x >>= 1;
+      b++;
+    }
+    return b;
+  };
+  char buf[160];
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  const char* arch = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.gcnArchName : "unknown";
+  snprintf(buf, sizeof(buf), "%s/cu%d/seg%d/leaf%d/chunk%d", arch, t->ctx->ncu, bucket(p->segs.size()),
+           bucket(p->leaves.size()), bucket(p->total_chunks));
+  return buf;
+}
+
+static bool cache_lookup(const std::string& key, dc_tune* out) {
+  FILE* f = fopen(cache_path().c_str(), "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    char k[200];
+    dc_tune tu{};
+    if (sscanf(line, "{\"key\": \"%199[^\"]\", \"block\": %u, \"wg_per_cu\": %u, \"tile_chunks\": %u}", k, &tu.block,
+               &tu.wg_per_cu, &tu.tile_chunks) == 4 &&
+        key == k && check_tune(tu) == DC_OK) {
+      *out = tu;
+      found = true;  // the last entry wins
+    }
+  }
+  fclose(f);
+  clear_error();
+  return found;
+}
+
+static void cache_store(const std::string& key, const dc_tune& tu, double us) {
+  const std::string path = cache_path();
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) mkdir(path.substr(0, slash).c_str(), 0755);  // may already exist
+  FILE* f = fopen(path.c_str(), "a");
+  if (!f) return;
+  fprintf(f, "{\"key\": \"%s\", \"block\": %u, \"wg_per_cu\": %u, \"tile_chunks\": %u, \"us\": %.1f}\n", key.c_str(),
+          tu.block, tu.wg_per_cu, tu.tile_chunks, us);
+  fclose(f);
+}
+
+static dc_status batch_args(dc_tree t, const dc_kernel_args* a, LeafArgs* la) {
+  if (!a) return fail(DC_E_INVAL, "null kernel args");
+  if (a->mode != DC_MODE_RESOLVED || a->select != DC_SELECT_ALL_LEAVES || a->iters != 1)
+    return fail(DC_E_INVAL, "the batched kernel runs RESOLVED, ALL_LEAVES, one pass");
+  memset(la, 0, sizeof(*la));
+  la->a = a->a;
+  la->b = a->b;
+  la->af = a->af;
+  la->bf = a->bf;
+  la->out = (uint8_t*)a->d_out;
+  if (la->out && a->out_bytes < t->plan->out_bytes) return fail(DC_E_RANGE, "d_out smaller than the leaf image");
+  if (la->out && ((uintptr_t)la->out & 15)) return fail(DC_E_RANGE, "d_out must be 16-byte aligned");
+  return DC_OK;
+}
+
+static dc_status resolve_tune(dc_tree t, const dc_tune* tune, dc_tune* out) {
+  if (tune) {
+    *out = *tune;
+    if (!out->block) out->block = kDefaultTune.block;
+    if (!out->wg_per_cu) out->wg_per_cu = kDefaultTune.wg_per_cu;
+    if (!out->tile_chunks) out->tile_chunks = kDefaultTune.tile_chunks;
+  } else if (!cache_lookup(tune_key(t), out)) {
+    *out = kDefaultTune;
+  }
+  return check_tune(*out);
+}
+
+// enqueue the persistent launch (and its counter reset) on s
+static dc_status enqueue_batch(dc_tree t, const LeafArgs& la, const dc_tune& tu, uint32_t flags, hipStream_t s) {
+  dc_plan p = t->plan;
+  if (!p->leaves.empty()) DC_TRY(tree_ensure_tiles(t, tu.tile_chunks, s));
+  hipError_t e = launch_reset_counters(t->tab.hdr, s);
+  if (e == hipSuccess) {
+    const uint64_t ntiles = p->leaves.empty() ? 0 : ntiles_for(p, tu.tile_chunks);
+    e = launch_batch(t->tab, la, flags, tu.block, (uint32_t)t->ctx->ncu * tu.wg_per_cu, tu.tile_chunks, ntiles, s);
+  }
+  if (e != hipSuccess) return fail(DC_E_HIP, "batch launch: %s", hipGetErrorString(e));
+  return DC_OK;
+}
+
+static dc_status batch_state(dc_tree t, uint32_t flags) {
+  if (flags & ~(uint32_t)(DC_BATCH_ATTACH | DC_BATCH_DETACH)) return fail(DC_E_INVAL, "flags %#x", flags);
+  if ((flags & DC_BATCH_ATTACH) && t->attached) return fail(DC_E_STATE, "ATTACH on an attached tree");
+  if (!(flags & DC_BATCH_ATTACH) && !t->attached) return fail(DC_E_STATE, "the tree is staged: pass ATTACH");
+  return DC_OK;
+}
+
+}  // namespace dc
+
+using namespace dc;
+
+struct dc_graph_s {
+  dc_tree tree = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint8_t* up = nullptr;    // pinned staged image
+  uint8_t* down = nullptr;  // pinned arena copy
+};
+
+extern "C" {
+
+dc_status dc_batch_run(dc_tree t, const dc_kernel_args* a, const dc_tune* tune, uint32_t flags, void* stream) {
+  if (!t || t->released) return fail(DC_E_INVAL, "dc_batch_run: null or released tree");
+  DC_TRY(batch_state(t, flags));
+  LeafArgs la;
+  DC_TRY(batch_args(t, a, &la));
+  dc_tune tu;
+  DC_TRY(resolve_tune(t, tune, &tu));
+  DC_HIP(hipSetDevice(t->ctx->device));
+  DC_TRY(enqueue_batch(t, la, tu, flags, (hipStream_t)stream));
+  if (flags & DC_BATCH_DETACH) t->attached = false;
+  else t->attached = true;
+  return DC_OK;
+}
+
+dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune* out) {
+  if (!t || t->released || !out) return fail(DC_E_INVAL, "dc_autotune: null argument");
+  if (t->attached) return fail(DC_E_STATE, "dc_autotune needs a staged tree");
+  LeafArgs la;
+  DC_TRY(batch_args(t, a, &la));
+  if (reps == 0) reps = 3;
+  DC_HIP(hipSetDevice(t->ctx->device));
+  hipStream_t s;
+  DC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipEvent_t e0, e1;
+  DC_HIP(hipEventCreate(&e0));
+  DC_HIP(hipEventCreate(&e1));
+  const uint32_t flags = DC_BATCH_ATTACH | DC_BATCH_DETACH;
+  std::vector<dc_tune> cands;
+  for (uint32_t block : {256u, 512u})
+    for (uint32_t tile : {512u, 1024u, 2048u})
+      for (uint32_t wg : {2u, 4u, 8u}) {
+        dc_tune c{block, wg, tile, 0};
+        if (check_tune(c) == DC_OK) cands.push_back(c);
+      }
+  clear_error();
+  dc_tune best = kDefaultTune;
+  double best_us = 1e300;
+  dc_status st = DC_OK;
+  for (const dc_tune& c : cands) {
+    st = enqueue_batch(t, la, c, flags, s);  // warm-up, also builds the tile index
+    if (st != DC_OK) break;
+    std::vector<float> ms;
+    for (uint32_t r = 0; r < reps && st == DC_OK; r++) {
+      hipEventRecord(e0, s);
+      st = enqueue_batch(t, la, c, flags, s);
+      hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) st = fail(DC_E_HIP, "autotune sync");
+      float m = 0;
+      hipEventElapsedTime(&m, e0, e1);
+      ms.push_back(m);
+    }
+    if (st != DC_OK) break;
+    std::sort(ms.begin(), ms.end());
+    const double us = 1000.0 * ms[ms.size() / 2];
+    if (us < best_us) {
+      best_us = us;
+      best = c;
+    }
+  }
+  hipStreamSynchronize(s);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipStreamDestroy(s);
+  DC_TRY(st);
+  DC_TRY(tree_check(t, nullptr));
+  cache_store(tune_key(t), best, best_us);
+  *out = best;
+  return DC_OK;
+}
+
+dc_status dc_graph_create(dc_tree t, const dc_kernel_args* a, const dc_tune* tune, uint32_t flags, int upload,
+                          int download, dc_graph* out) {
+  if (!out) return fail(DC_E_INVAL, "dc_graph_create: out is null");
+  *out = nullptr;
+  if (!t || t->released) return fail(DC_E_INVAL, "dc_graph_create: null or released tree");
+  if (flags != (DC_BATCH_ATTACH | DC_BATCH_DETACH))
+    return fail(DC_E_INVAL, "a graph replays ATTACH|DETACH so that every replay starts from the staged image");
+  if (t->attached) return fail(DC_E_STATE, "dc_graph_create needs a staged tree");
+  LeafArgs la;
+  DC_TRY(batch_args(t, a, &la));
+  dc_tune tu;
+  DC_TRY(resolve_tune(t, tune, &tu));
+  DC_HIP(hipSetDevice(t->ctx->device));
+  dc_plan p = t->plan;
+  dc_graph g = new dc_graph_s();
+  g->tree = t;
+  auto cleanup = [&](dc_status st) {
+    dc_graph_destroy(g);
+    return st;
+  };
+  hipStream_t cs;
+  DC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  // the tile index is built outside the graph; the graph only replays the launch
+  if (!p->leaves.empty()) {
+    dc_status st = tree_ensure_tiles(t, tu.tile_chunks, cs);
+    if (st != DC_OK) return cleanup(st);
+  }
+  if (upload) {
+    if (hipHostMalloc((void**)&g->up, std::max<uint64_t>(p->arena_bytes, 1), hipHostMallocDefault) != hipSuccess)
+      return cleanup(fail(DC_E_NOMEM, "pinned image of %llu bytes", (unsigned long long)p->arena_bytes));
+    // the staged image is what the arena holds now: read it back once
+    if (p->arena_bytes) DC_HIP(hipMemcpyAsync(g->up, t->arena, p->arena_bytes, hipMemcpyDeviceToHost, cs));
+  }
+  if (download && hipHostMalloc((void**)&g->down, std::max<uint64_t>(p->arena_bytes, 1), hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(DC_E_NOMEM, "pinned image of %llu bytes", (unsigned long long)p->arena_bytes));
+  DC_HIP(hipStreamSynchronize(cs));
+  DC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  if (upload && p->arena_bytes) hipMemcpyAsync(t->arena, g->up, p->arena_bytes, hipMemcpyHostToDevice, cs);
+  dc_status st = enqueue_batch(t, la, tu, flags, cs);
+  if (download && p->arena_bytes) hipMemcpyAsync(g->down, t->arena, p->arena_bytes, hipMemcpyDeviceToHost, cs);
+  hipError_t e = hipStreamEndCapture(cs, &g->graph);
+  hipStreamDestroy(cs);
+  if (st != DC_OK) return cleanup(st);
+  if (e != hipSuccess) return cleanup(fail(DC_E_HIP, "graph capture: %s", hipGetErrorString(e)));
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return cleanup(fail(DC_E_HIP, "graph instantiate: %s", hipGetErrorString(e)));
+  *out = g;
+  return DC_OK;
+}
+
+dc_status dc_graph_launch(dc_graph g, void* stream) {
+  if (!g || !g->exec) return fail(DC_E_INVAL, "dc_graph_launch: null graph");
+  if (g->tree->attached) return fail(DC_E_STATE, "dc_graph_launch needs the tree staged");
+  DC_HIP(hipSetDevice(g->tree->ctx->device));
+  DC_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return DC_OK;
+}
+
+dc_status dc_graph_destroy(dc_graph g) {
+  if (!g) return fail(DC_E_INVAL, "dc_graph_destroy: null graph");
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  if (g->up || g->down) hipDeviceSynchronize();
+  if (g->up) hipHostFree(g->up);
+  if (g->down) hipHostFree(g->down);
+  delete g;
+  return DC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,306 @@
+// libdc host core: errors, thread pool, context and pinned staging, schema.
+#include "dc_host.h"
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+namespace dc {
+
+static thread_local std::string g_err;
+
+dc_status fail(dc_status code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+// ---- pool --------------------------------------------------------------------------
+
+Pool::Pool(int nthreads) {
+  for (int i = 1; i < nthreads; i++) workers_.emplace_back([this] { loop(); });
+}
+
+Pool::~Pool() {
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    stop_ = true;
+  }
+  cv_.notify_all();
+  for (auto& w : workers_) w.join();
+}
+
+void Pool::loop() {
+  uint64_t seen = 0;
+  for (;;) {
+    const std::function<void(int)>* fn;
+    int n;
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+      if (stop_) return;
+      seen = gen_;
+      fn = fn_;
+      n = n_;
+      active_++;
+    }
+    for (int i; (i = next_.fetch_add(1)) < n;) (*fn)(i);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--active_ == 0) done_cv_.notify_all();
+    }
+  }
+}
+
+void Pool::run(int n, const std::function<void(int)>& fn) {
+  if (n <= 0) return;
+  if (workers_.empty() || n == 1) {
+    for (int i = 0; i < n; i++) fn(i);
+    return;
+  }
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    fn_ = &fn;
+    n_ = n;
+    next_.store(0);
+    gen_++;
+  }
+  cv_.notify_all();
+  for (int i; (i = next_.fetch_add(1)) < n;) fn(i);
+  std::unique_lock<std::mutex> lk(mu_);
+  done_cv_.wait(lk, [&] { return active_ == 0 && next_.load() >= n; });
+  fn_ = nullptr;
+}
+
+// ---- staging ----------------------------------------------------------------------------
+
+// Writes destination range [lo, hi) into buf: the bytes of every piece that
+// overlaps it, zeros elsewhere. Split across the pool in ~4 MiB parts.
+static void pack_range(dc_ctx ctx, uint8_t* buf, uint64_t lo, uint64_t hi, const PieceSource& src) {
+  const uint64_t part = 4ull << 20;
+  const int nparts = (int)((hi - lo + part - 1) / part);
+  ctx->pool->run(nparts, [&](int k) {
+    const uint64_t plo = lo + (uint64_t)k * part;
+    const uint64_t phi = std::min(hi, plo + part);
+    uint64_t cur = plo;
+    for (uint64_t i = src.first_ending_after(plo); i < src.n && cur < phi; i++) {
+      const Piece pc = src.at(i);
+      if (pc.off >= phi) break;
+      const uint64_t a = std::max(pc.off, plo);
+      const uint64_t b = std::min(pc.off + pc.bytes, phi);
+      if (a > cur) memset(buf + (cur - lo), 0, a - cur);
+      if (b > a) memcpy(buf + (a - lo), (const uint8_t*)pc.src + (a - pc.off), b - a);
+      cur = std::max(cur, b);
+    }
+    if (cur < phi) memset(buf + (cur - lo), 0, phi - cur);
+  });
+}
+
+static dc_status ring_slot(dc_ctx ctx, int* k) {
+  *k = ctx->next;
+  ctx->next = (ctx->next + 1) % dc_ctx_s::kRing;
+  if (ctx->pending[*k]) {
+    DC_HIP(hipEventSynchronize(ctx->ev[*k]));
+    ctx->pending[*k] = false;
+  }
+  return DC_OK;
+}
+
+dc_status ctx_wait_ring(dc_ctx ctx) {
+  for (int k = 0; k < dc_ctx_s::kRing; k++)
+    if (ctx->pending[k]) {
+      DC_HIP(hipEventSynchronize(ctx->ev[k]));
+      ctx->pending[k] = false;
+    }
+  return DC_OK;
+}
+
+dc_status upload_source(dc_ctx ctx, uint8_t* dst, uint64_t total, const PieceSource& src, hipStream_t s) {
+  for (uint64_t lo = 0; lo < total; lo += ctx->chunk_bytes) {
+    const uint64_t hi = std::min(total, lo + ctx->chunk_bytes);
+    int k;
+    DC_TRY(ring_slot(ctx, &k));
+    pack_range(ctx, ctx->ring[k], lo, hi, src);
+    DC_HIP(hipMemcpyAsync(dst + lo, ctx->ring[k], hi - lo, hipMemcpyHostToDevice, s));
+    DC_HIP(hipEventRecord(ctx->ev[k], s));
+    ctx->pending[k] = true;
+  }
+  return DC_OK;
+}
+
+dc_status upload_pieces(dc_ctx ctx, uint8_t* dst, uint64_t total, const std::vector<Piece>& pieces, hipStream_t s) {
+  PieceSource src;
+  src.n = pieces.size();
+  src.at = [&](uint64_t i) { return pieces[i]; };
+  src.first_ending_after = [&](uint64_t x) {
+    return (uint64_t)(std::upper_bound(pieces.begin(), pieces.end(), x,
+                                       [](uint64_t v, const Piece& p) { return v < p.off + p.bytes; }) -
+                      pieces.begin());
+  };
+  return upload_source(ctx, dst, total, src, s);
+}
+
+dc_status download(dc_ctx ctx, const uint8_t* src, uint64_t lo, uint64_t hi, hipStream_t s,
+                   const std::function<void(const uint8_t*, uint64_t, uint64_t)>& consume) {
+  DC_TRY(ctx_wait_ring(ctx));
+  const uint64_t ch = ctx->chunk_bytes;
+  const uint64_t n = hi > lo ? (hi - lo + ch - 1) / ch : 0;
+  const int R = dc_ctx_s::kRing;
+  auto issue = [&](uint64_t i) -> dc_status {
+    const int k = (int)(i % R);
+    const uint64_t a = lo + i * ch, b = std::min(hi, a + ch);
+    DC_HIP(hipMemcpyAsync(ctx->ring[k], src + a, b - a, hipMemcpyDeviceToHost, s));
+    DC_HIP(hipEventRecord(ctx->ev[k], s));
+    ctx->pending[k] = true;
+    return DC_OK;
+  };
+  for (uint64_t i = 0; i < n && i < (uint64_t)R; i++) DC_TRY(issue(i));
+  for (uint64_t i = 0; i < n; i++) {
+    const int k = (int)(i % R);
+    DC_HIP(hipEventSynchronize(ctx->ev[k]));
+    ctx->pending[k] = false;
+    const uint64_t a = lo + i * ch, b = std::min(hi, a + ch);
+    consume(ctx->ring[k], a, b);
+    if (i + R < n) DC_TRY(issue(i + R));
+  }
+  return DC_OK;
+}
+
+// ---- schema ------------------------------------------------------------------------------
+
+static bool valid_kind(uint32_t k) { return k <= DC_KIND_U8; }
+
+}  // namespace dc
+
+using namespace dc;
+
+extern "C" {
+
+const char* dc_last_error(void) { return dc::g_err.c_str(); }
+
+const char* dc_version(void) { return "libdc 0.1 (gfx950)"; }
+
+dc_status dc_ctx_create(int device, dc_ctx* out) {
+  if (!out) return fail(DC_E_INVAL, "dc_ctx_create: out is null");
+  *out = nullptr;
+  int ndev = 0;
+  DC_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(DC_E_INVAL, "dc_ctx_create: device %d of %d", device, ndev);
+  DC_HIP(hipSetDevice(device));
+  dc_ctx c = new dc_ctx_s();
+  c->device = device;
+  c->ncu = device_cu_count();
+  for (int k = 0; k < dc_ctx_s::kRing; k++) {
+    if (hipHostMalloc((void**)&c->ring[k], c->chunk_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming) != hipSuccess) {
+      dc_ctx_destroy(c);
+      return fail(DC_E_NOMEM, "dc_ctx_create: pinned staging of %d x %llu bytes", dc_ctx_s::kRing,
+                  (unsigned long long)c->chunk_bytes);
+    }
+  }
+  if (hipHostMalloc((void**)&c->small, 4096, hipHostMallocDefault) != hipSuccess) {
+    dc_ctx_destroy(c);
+    return fail(DC_E_NOMEM, "dc_ctx_create: pinned result buffer");
+  }
+  unsigned hw = std::thread::hardware_concurrency();
+  c->pool = new Pool((int)std::max(1u, std::min(hw ? hw : 1u, 32u)));
+  *out = c;
+  clear_error();
+  return DC_OK;
+}
+
+dc_status dc_ctx_destroy(dc_ctx c) {
+  if (!c) return fail(DC_E_INVAL, "dc_ctx_destroy: null context");
+  hipSetDevice(c->device);
+  for (int k = 0; k < dc_ctx_s::kRing; k++) {
+    if (c->pending[k]) hipEventSynchronize(c->ev[k]);
+    if (c->ev[k]) hipEventDestroy(c->ev[k]);
+    if (c->ring[k]) hipHostFree(c->ring[k]);
+  }
+  if (c->small) hipHostFree(c->small);
+  delete c->pool;
+  delete c;
+  return DC_OK;
+}
+
+dc_status dc_schema_create(dc_schema* out) {
+  if (!out) return fail(DC_E_INVAL, "dc_schema_create: out is null");
+  *out = new dc_schema_s();
+  return DC_OK;
+}
+
+dc_status dc_schema_destroy(dc_schema s) {
+  if (!s) return fail(DC_E_INVAL, "dc_schema_destroy: null schema");
+  delete s;
+  return DC_OK;
+}
+
+dc_status dc_schema_describe(dc_schema s, const char* name, uint32_t size, uint32_t align, const dc_field* fields,
+                             uint32_t nfields, uint32_t* out_type_id) {
+  if (!s || (!fields && nfields)) return fail(DC_E_INVAL, "dc_schema_describe: null argument");
+  if (s->types.size() >= kMaxTypes) return fail(DC_E_INVAL, "dc_schema_describe: more than %u types", kMaxTypes);
+  if (size == 0 || align == 0 || (align & (align - 1)))
+    return fail(DC_E_INVAL, "dc_schema_describe(%s): size %u align %u", name ? name : "?", size, align);
+  if (nfields > kMaxFields)
+    return fail(DC_E_INVAL, "dc_schema_describe(%s): %u pointer fields (max %u)", name ? name : "?", nfields,
+                kMaxFields);
+  TypeDesc t;
+  t.name = name ? name : "";
+  t.size = size;
+  t.align = align;
+  t.described = true;
+  t.fields.assign(fields, fields + nfields);
+  std::vector<uint8_t> is_ptr(size, 0);
+  for (uint32_t i = 0; i < nfields; i++) {
+    const dc_field& f = fields[i];
+    if (f.offset % 8 || f.offset + 8 > size)
+      return fail(DC_E_INVAL, "dc_schema_describe(%s): pointer field %u at offset %u (must be 8-aligned, inside %u)",
+                  t.name.c_str(), i, f.offset, size);
+    if (!valid_kind(f.kind)) return fail(DC_E_INVAL, "dc_schema_describe(%s): field %u kind %u", t.name.c_str(), i, f.kind);
+    if (f.kind == DC_KIND_STRUCT && f.type_id >= kMaxTypes)
+      return fail(DC_E_INVAL, "dc_schema_describe(%s): field %u type id %u", t.name.c_str(), i, f.type_id);
+    for (uint32_t b = f.offset; b < f.offset + 8; b++) {
+      if (is_ptr[b]) return fail(DC_E_INVAL, "dc_schema_describe(%s): pointer fields overlap", t.name.c_str());
+      is_ptr[b] = 1;
+    }
+    if (f.count_offset >= 0) {
+      if ((f.count_bytes != 4 && f.count_bytes != 8) || f.count_offset % f.count_bytes ||
+          (uint64_t)f.count_offset + f.count_bytes > size)
+        return fail(DC_E_INVAL, "dc_schema_describe(%s): field %u count member at %d (%u bytes)", t.name.c_str(), i,
+                    f.count_offset, f.count_bytes);
+      if (f.count_mult == 0) return fail(DC_E_INVAL, "dc_schema_describe(%s): field %u count_mult 0", t.name.c_str(), i);
+    } else if (f.count_offset != -1) {
+      return fail(DC_E_INVAL, "dc_schema_describe(%s): field %u count_offset %d", t.name.c_str(), i, f.count_offset);
+    }
+  }
+  for (uint32_t i = 0; i < nfields; i++) {
+    const dc_field& f = fields[i];
+    if (f.count_offset >= 0)
+      for (uint32_t b = (uint32_t)f.count_offset; b < (uint32_t)f.count_offset + f.count_bytes; b++)
+        if (is_ptr[b]) return fail(DC_E_INVAL, "dc_schema_describe(%s): count member overlaps a pointer", t.name.c_str());
+  }
+  t.order.resize(nfields);
+  for (uint32_t i = 0; i < nfields; i++) t.order[i] = i;
+  std::sort(t.order.begin(), t.order.end(), [&](uint32_t a, uint32_t b) { return fields[a].offset < fields[b].offset; });
+  t.pos.resize(nfields);
+  for (uint32_t k = 0; k < nfields; k++) t.pos[t.order[k]] = k;
+  uint32_t run = 0;
+  for (uint32_t k = 0; k <= nfields; k++) {
+    const uint32_t end = k < nfields ? fields[t.order[k]].offset : size;
+    if (end > run) t.plain_runs.push_back({run, end});
+    run = end + 8;
+  }
+  s->types.push_back(std::move(t));
+  if (out_type_id) *out_type_id = (uint32_t)(s->types.size() - 1);
+  return DC_OK;
+}
+
+}  // extern "C"

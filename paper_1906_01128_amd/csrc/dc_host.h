@@ -1,0 +1,200 @@
+// Host-side objects of libdc (C++17). Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "dc.h"
+#include "dc_internal.h"
+
+namespace dc {
+
+// ---- errors -----------------------------------------------------------------------
+dc_status fail(dc_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define DC_HIP(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return ::dc::fail(DC_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define DC_TRY(expr)              \
+  do {                            \
+    dc_status s_ = (expr);        \
+    if (s_ != DC_OK) return s_;   \
+  } while (0)
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// ---- a small fork-join pool -------------------------------------------------------------
+class Pool {
+ public:
+  explicit Pool(int nthreads);
+  ~Pool();
+  int size() const { return (int)workers_.size() + 1; }
+  // runs fn(i) for every i in [0, n); the caller takes part; returns when all are done
+  void run(int n, const std::function<void(int)>& fn);
+
+ private:
+  void loop();
+  std::vector<std::thread> workers_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)>* fn_ = nullptr;
+  int n_ = 0;
+  std::atomic<int> next_{0};
+  int active_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
+// ---- staging: pinned ring of chunks between pageable host memory and the device ---------------
+// A "piece" is a run of bytes at a fixed destination offset; gaps between
+// pieces are written as zeros.
+struct Piece {
+  uint64_t off;       // destination offset
+  const void* src;    // host bytes
+  uint64_t bytes;
+};
+
+struct dc_ctx_impl;
+
+}  // namespace dc
+
+struct dc_ctx_s {
+  int device = 0;
+  int ncu = 256;
+  static constexpr int kRing = 4;
+  uint64_t chunk_bytes = 64ull << 20;
+  uint8_t* ring[kRing] = {};
+  hipEvent_t ev[kRing] = {};
+  bool pending[kRing] = {};
+  int next = 0;
+  uint8_t* small = nullptr;  // pinned scratch for header reads
+  dc::Pool* pool = nullptr;
+};
+
+namespace dc {
+
+// Copies `pieces` (sorted by off, non-overlapping) into device memory
+// [0, total) at `dst`: packed through the pinned ring by the pool, zeros
+// between pieces, each chunk sent with hipMemcpyAsync on `s` while the next
+// one is packed.
+dc_status upload_pieces(dc_ctx ctx, uint8_t* dst, uint64_t total, const std::vector<Piece>& pieces, hipStream_t s);
+// Same, with pieces given by a callback for the objects of a plan (used for
+// the arena: millions of objects, described without building a vector).
+struct PieceSource {
+  uint64_t n;
+  std::function<Piece(uint64_t)> at;  // pieces in offset order
+  std::function<uint64_t(uint64_t)> first_ending_after;  // first piece with off + bytes > x
+};
+dc_status upload_source(dc_ctx ctx, uint8_t* dst, uint64_t total, const PieceSource& src, hipStream_t s);
+// Transfers device [lo, hi) back through the ring; consume(buf, clo, chi)
+// is called, in order, for each chunk [clo, chi) as it lands.
+dc_status download(dc_ctx ctx, const uint8_t* src, uint64_t lo, uint64_t hi, hipStream_t s,
+                   const std::function<void(const uint8_t*, uint64_t, uint64_t)>& consume);
+dc_status ctx_wait_ring(dc_ctx ctx);
+
+// ---- schema -----------------------------------------------------------------------
+struct TypeDesc {
+  std::string name;
+  uint32_t size = 0, align = 1;
+  bool described = false;
+  std::vector<dc_field> fields;   // as given
+  std::vector<uint32_t> order;    // field indices by ascending offset
+  std::vector<uint32_t> pos;      // position of field i in `order`
+  std::vector<std::pair<uint32_t, uint32_t>> plain_runs;  // [lo, hi) byte runs that are not pointers
+};
+
+}  // namespace dc
+
+struct dc_schema_s {
+  std::vector<dc::TypeDesc> types;
+};
+
+namespace dc {
+
+// ---- plan -------------------------------------------------------------------------
+struct Obj {
+  uint64_t host;
+  uint64_t off;
+  uint64_t bytes;
+  uint64_t count;
+  uint32_t kind;
+  uint32_t type;
+  uint32_t parent;      // first discoverer, kNone for a root
+  uint32_t sobj;        // index among slotted struct arrays, kNone otherwise
+  uint64_t parent_rel;  // offset of the discovering slot inside the parent
+  uint32_t depth;       // pointer hops from the root
+  uint32_t pad;
+};
+
+class FlatMap {  // host address -> object index
+ public:
+  void reserve(uint64_t n);
+  uint32_t find(uint64_t key) const;
+  void insert(uint64_t key, uint32_t val);
+
+ private:
+  void grow();
+  std::vector<uint64_t> keys_;
+  std::vector<uint32_t> vals_;
+  uint64_t mask_ = 0, n_ = 0;
+};
+
+}  // namespace dc
+
+struct dc_plan_s {
+  std::vector<dc::TypeDesc> types;
+  std::vector<dc::DevType> dev_types;
+  uint32_t root_type = 0;
+  uint64_t align = 64;
+  std::vector<uint64_t> roots;  // host addresses as given
+  std::vector<uint32_t> root_obj;
+  std::vector<dc::Obj> objs;
+  dc::FlatMap map;
+  // slotted struct arrays (arena order) and their slot prefix
+  std::vector<dc::DevSObj> sobj;
+  std::vector<uint64_t> sobj_pre;
+  std::vector<uint32_t> slot_target;  // per slot: target object or kNone
+  // relocation units
+  std::vector<dc::DevSeg> segs;
+  std::vector<uint32_t> targets;
+  // leaves (FP32/FP64 arrays with >= 1 element), arena order
+  std::vector<uint32_t> leaves;
+  std::vector<uint64_t> leaf_pre, leaf_info, leaf_slot, leaf_out;
+  uint64_t out_bytes = 0, total_chunks = 0, total_hops = 0;
+  // host copies of the object table as the device sees it
+  std::vector<uint64_t> obj_host, obj_off;
+  dc::ScratchLayout sl{};
+  uint64_t arena_bytes = 0, payload_bytes = 0, leaf_bytes = 0, nslots_nonnull = 0;
+};
+
+struct dc_tree_s {
+  dc_ctx ctx = nullptr;
+  dc_plan plan = nullptr;
+  uint8_t* arena = nullptr;
+  uint8_t* scratch = nullptr;
+  dc::Tables tab{};
+  bool attached = false;
+  bool released = false;
+  bool paths_uploaded = false;
+  uint32_t tile_T = 0;  // tile size the tile index currently holds
+};
+
+namespace dc {
+dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, const void* const* roots,
+                     uint64_t nroots, uint64_t align);
+dc_status tree_ensure_tiles(dc_tree t, uint32_t T, hipStream_t s);
+dc_status tree_check(dc_tree t, hipStream_t s);
+uint64_t ntiles_for(const dc_plan_s* p, uint32_t T);
+}  // namespace dc

@@ -1,0 +1,179 @@
+// Internal layouts shared by the host core and the HIP kernels of libdc.
+// Everything a kernel reads lives in the caller's scratch buffer at offsets
+// fixed by the plan (ScratchLayout); the arena holds only the copied objects.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dc.h"
+
+namespace dc {
+
+constexpr uint32_t kMaxFields = 16;   // pointer members per struct type
+constexpr uint32_t kMaxTypes = 64;
+constexpr uint32_t kMaxChainSteps = 32;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Relocation work units ("segments"): a contiguous range of the global slot
+// enumeration (struct objects in arena order, elements in index order,
+// pointer members in ascending offset order) and the distinct objects its
+// non-null slots point to. A workgroup stages those objects' (key -> object)
+// pairs in an LDS hash table and translates every slot of the range.
+constexpr uint32_t kSegMaxTargets = 1024;  // distinct targets per unit
+constexpr uint32_t kSegHashSlots = 2048;   // LDS hash capacity (load <= 1/2)
+constexpr uint32_t kSegMaxSObjs = 512;     // struct objects spanned per unit
+constexpr uint64_t kSegMaxSlots = 16384;   // slots per unit
+
+constexpr uint32_t kChunk = 16;            // bytes per vector access of the leaf kernels
+constexpr uint32_t kMinTileChunks = 256;   // smallest compute tile the scratch is sized for
+constexpr uint32_t kMaxTileChunks = 1024;  // largest compute tile (LDS leaf table, 32 KiB)
+
+// Struct type as the kernels see it: pointer members sorted by offset.
+struct DevType {
+  uint32_t size;
+  uint32_t nptr;
+  uint32_t ptr_off[kMaxFields];
+  uint32_t kind[kMaxFields];
+  uint32_t ptype[kMaxFields];
+  int32_t cnt_off[kMaxFields];
+  uint32_t cnt_bytes[kMaxFields];
+  uint32_t cnt_mult[kMaxFields];
+  uint64_t fixed[kMaxFields];
+};
+
+struct DevSObj {  // one struct array placed in the arena
+  uint64_t off;
+  uint64_t count;
+  uint32_t type;
+  uint32_t obj;
+};
+
+struct DevSeg {
+  uint64_t slot_lo, slot_hi;  // slot range [lo, hi)
+  uint64_t tgt_lo, tgt_hi;    // range in the target list
+  uint32_t sobj_lo, sobj_hi;  // struct objects overlapping the slot range
+  uint32_t pad[2];
+};
+
+// Leaf (FP32/FP64 array with >= 1 element) records for the compute kernels.
+// info = bytes | kind << 56.
+constexpr int kLeafKindShift = 56;
+
+struct DevPath {  // pointer path by which the walk first reached a leaf
+  uint64_t root_off;
+  uint32_t hop_lo, nhops;
+};
+
+// Header at offset 0 of scratch.
+struct DevHeader {
+  uint64_t arena;  // device address of the arena (B)
+  uint64_t nobj, nsobj, nseg, nleaves, nslots;
+  uint64_t total_chunks;
+  // device-side error reporting (sticky until the host clears it)
+  uint32_t err_count;
+  uint32_t err_code;
+  uint64_t err_slot;  // arena offset of the first bad slot
+  // persistent kernel work queue and phase counters
+  uint32_t queue;
+  uint32_t doneA, doneB, doneC;
+  uint32_t spin_fail;
+  uint32_t pad0;
+  // chain resolution result
+  uint64_t chain_addr, chain_count;
+  uint32_t chain_kind, chain_status;
+  uint64_t pad1[8];
+};
+
+enum DevErr : uint32_t {
+  kErrNone = 0,
+  kErrUnknownPtr = 1,  // a slot value that is not a planned array start
+  kErrNullChain = 2,
+  kErrIndex = 3,
+  kErrKind = 4,
+  kErrSpin = 5,        // persistent kernel wait bound hit
+  kErrWild = 6         // a pointer followed by a kernel lies outside the arena
+};
+
+struct ScratchLayout {
+  uint64_t header, types, obj_host, obj_off, sobj, sobj_pre, segs, targets;
+  uint64_t leaf_slot, leaf_pre, leaf_info, leaf_out;
+  uint64_t tile_first, paths, hops;
+  uint64_t static_end;  // [0, static_end) is uploaded with every deep copy
+  uint64_t total;
+};
+
+// Arguments of the compute kernels. A pass reads each leaf from the arena
+// (or, when src_out is set, from its place in the out image) and writes it
+// to the arena (out == null) or to the out image.
+struct LeafArgs {
+  double a, b;
+  float af, bf;
+  uint8_t* out;
+  uint32_t src_out;
+  uint32_t pad;
+};
+
+// One chain for the device resolver: per step the byte offset of the pointer
+// member, where its count lives, the element size of the array it points to
+// and the index to continue at.
+struct ChainArgs {
+  uint64_t root_off;
+  uint32_t nsteps;
+  uint32_t pad;
+  uint32_t field_off[kMaxChainSteps];
+  int32_t cnt_off[kMaxChainSteps];
+  uint32_t cnt_bytes[kMaxChainSteps];
+  uint32_t cnt_mult[kMaxChainSteps];
+  uint32_t elem_size[kMaxChainSteps];
+  uint32_t kind[kMaxChainSteps];
+  uint64_t fixed[kMaxChainSteps];
+  uint64_t index[kMaxChainSteps];
+};
+
+// Per-access chain walk: p = root; for each hop p = *(p + hop_off[h]).
+struct HopArgs {
+  uint64_t root_off;
+  uint32_t nhops;
+  uint32_t pad;
+  uint64_t hop_off[kMaxChainSteps];
+};
+
+// ---- launchers (dc_kernels.hip) ------------------------------------------------
+struct Tables {  // device addresses of the scratch tables
+  DevHeader* hdr;
+  const DevType* types;
+  const uint64_t* obj_host;
+  const uint64_t* obj_off;
+  const DevSObj* sobj;
+  const uint64_t* sobj_pre;  // nsobj + 1 entries (slot prefix)
+  const DevSeg* segs;
+  const uint32_t* targets;
+  const uint64_t* leaf_slot;
+  const uint64_t* leaf_pre;  // nleaves + 1 entries (16-byte chunk prefix)
+  const uint64_t* leaf_info;
+  const uint64_t* leaf_out;
+  uint32_t* tile_first;
+  const DevPath* paths;
+  const uint64_t* hops;
+  uint8_t* arena;
+  uint64_t arena_bytes;
+  uint64_t nseg, nleaves, total_chunks;
+};
+
+hipError_t launch_relocate(const Tables& t, bool attach, hipStream_t s);
+hipError_t launch_resolve_chain(const Tables& t, const ChainArgs& c, hipStream_t s);
+hipError_t launch_tile_index(const Tables& t, uint32_t tile_chunks, uint64_t ntiles, hipStream_t s);
+hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint32_t tile_chunks, uint64_t ntiles,
+                             bool deref_each, hipStream_t s);
+// one FP32/FP64 array whose address the chain resolver left in the header
+hipError_t launch_stream_resolved(const Tables& t, uint64_t count, uint32_t kind, const LeafArgs& la,
+                                  hipStream_t s);
+hipError_t launch_stream_deref(const Tables& t, const HopArgs& h, uint64_t count, uint32_t kind,
+                               const LeafArgs& la, hipStream_t s);
+hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
+                        uint32_t tile_chunks, uint64_t ntiles, hipStream_t s);
+hipError_t launch_reset_counters(DevHeader* hdr, hipStream_t s);
+int device_cu_count();
+
+}  // namespace dc

@@ -1,0 +1,128 @@
+"""GPU parity of the batched form: every structure's relocation and leaf
+kernel in one persistent launch, its HIP-graph replays, and the autotuner.
+Results must not depend on the tile shape."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import fixtures as fx
+import oracle as orc
+from tests.test_gpu_parity import Copy, assert_same_bytes, ctx  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _staged_after_kernel(c, iters):
+    """The staged image (host pointers in the slots) with every leaf advanced
+    by `iters` oracle passes."""
+    ref = orc.OracleCopy(c.t.types, c.t.root_type, c.t.roots, c.oracle.align, c.base)
+    ref.run_kernel(1.0001, 0.5, iters=iters, select="all")
+    img = c.raw_image()
+    ar = ref.arena()
+    for o in ref.objects():
+        if o["kind"] in (1, 2) and o["bytes"]:
+            lo, hi = int(o["off"]), int(o["off"]) + int(o["bytes"])
+            img[lo:hi] = ar[lo:hi]
+    return img
+
+
+def test_batch_md_attach(ctx):
+    t = fx.md(nsims=100)
+    c = Copy(ctx, t, relocate=False)
+    assert_same_bytes(c.device_arena(), c.raw_image(), "staged")
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=False)
+    c.oracle.run_kernel(1.0001, 0.5, iters=1, select="all")
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "batched attach+compute")
+    c.tree.check()
+    # the tree is attached now: plain kernels and chains work on it
+    assert c.tree.resolve_chain([(0, 3), (2, 0)], root_index=7) == c.oracle.resolve_chain(7, [(0, 3), (2, 0)])
+
+
+@pytest.mark.parametrize("tune", [None, dict(block=256, wg_per_cu=2, tile_chunks=256),
+                                  dict(block=512, wg_per_cu=8, tile_chunks=1024),
+                                  dict(block=1024, wg_per_cu=1, tile_chunks=1024),
+                                  dict(block=256, wg_per_cu=4, tile_chunks=512)])
+def test_batch_attach_detach_any_tile_shape(ctx, tune):
+    t = fx.md(seed=5, nsims=60, cells_lo=1, cells_hi=40, mean_atoms=5)
+    c = Copy(ctx, t, relocate=False)
+    want = _staged_after_kernel(c, 1)
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=tune)
+    assert_same_bytes(c.device_arena(), want, f"batched attach+compute+detach {tune}")
+    c.tree.check()
+
+
+def test_batch_wide_and_out_of_place(ctx):
+    t = fx.wide(seed=81, f1=16, f2=16, lo=1, hi=5000)
+    c = Copy(ctx, t, relocate=False)
+    n = c.plan.info().out_bytes
+    out = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    c.tree.batch_run(a=0.9999, b=-0.25, attach=True, detach=False, out=out)
+    want = np.zeros(n, np.uint8)
+    c.oracle.run_kernel(0.9999, -0.25, iters=1, select="all", out=want)
+    torch.cuda.synchronize()
+    assert_same_bytes(out.cpu().numpy(), want, "batched out-of-place image")
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "arena relocated, leaves untouched")
+
+
+def test_graph_replays(ctx):
+    t = fx.md(seed=6, nsims=40, cells_lo=2, cells_hi=30, mean_atoms=8)
+    c = Copy(ctx, t, relocate=False)
+    g = c.tree.graph(a=1.0001, b=0.5)
+    x = torch.ones(1 << 20, device="cuda")
+    for r in range(1, 4):
+        g.launch()
+        torch.cuda.synchronize()
+        assert_same_bytes(c.device_arena(), _staged_after_kernel(c, r), f"graph replay {r}")
+        x.mul_(1.5).add_(1.0)  # eager work between replays
+        torch.cuda.synchronize()
+    c.tree.check()
+    g.close()
+
+
+def test_graph_with_upload_restarts_from_image(ctx):
+    t = fx.md(seed=7, nsims=30, cells_lo=2, cells_hi=20, mean_atoms=8)
+    c = Copy(ctx, t, relocate=False)
+    want = _staged_after_kernel(c, 1)
+    g = c.tree.graph(a=1.0001, b=0.5, upload=True, download=True)
+    for r in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        assert_same_bytes(c.device_arena(), want, f"uploaded replay {r}")
+    g.close()
+
+
+def test_autotune_then_parity(ctx, tmp_path, monkeypatch):
+    monkeypatch.setenv("DC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    t = fx.md(seed=8, nsims=200, cells_lo=4, cells_hi=64, mean_atoms=16)
+    c = Copy(ctx, t, relocate=False)
+    choice = c.tree.autotune(reps=1)
+    assert choice["block"] in (256, 512, 1024)
+    assert (tmp_path / "tune.json").exists()
+    # the autotuner changed leaf values; copy again and run with the cached choice
+    t2 = fx.md(seed=8, nsims=200, cells_lo=4, cells_hi=64, mean_atoms=16)
+    c2 = Copy(ctx, t2, relocate=False)
+    c2.tree.batch_run(a=1.0001, b=0.5, attach=True)
+    c2.oracle.run_kernel(1.0001, 0.5, iters=1, select="all")
+    assert_same_bytes(c2.device_arena(), c2.oracle.arena(), "after autotune")
+
+
+@pytest.mark.slow
+def test_batch_md_full_size(ctx):
+    """10,000 simulations, ~7.8 M arrays, ~12 GB: one persistent launch,
+    compared with the oracle over the whole arena."""
+    fx.set_threads(0)
+    t = fx.md()
+    c = Copy(ctx, t, relocate=False)
+    info = c.plan.info()
+    print(f"[md full] objects {info.nobjects} slots {info.nslots_nonnull} arena {info.arena_bytes}", flush=True)
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True)
+    c.oracle.run_kernel(1.0001, 0.5, iters=1, select="all")
+    torch.cuda.synchronize()
+    got = c.arena[: c.plan.arena_bytes].cpu().numpy()
+    want = c.oracle.arena()
+    step = 1 << 30
+    for lo in range(0, len(want), step):
+        assert np.array_equal(got[lo:lo + step], want[lo:lo + step]), f"md full arena differs in GiB {lo >> 30}"
+    c.tree.check()

@@ -1,0 +1,98 @@
+"""The served form: jobs of mixed sizes admitted by budget, structures kept
+resident, work of several jobs overlapping on the device. Every job's result
+must be the same alone and in the mix, and equal to the oracle's."""
+import ctypes
+import random
+
+import numpy as np
+import pytest
+
+import fixtures as fx
+import oracle as orc
+from tests.test_gpu_parity import ctx  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+AB = [(1.0001, 0.5), (1.0001, -0.25), (0.9999, 0.5), (0.9999, -0.25)]
+
+
+def _structures(n, bytes_hi, seed=0):
+    return [fx.broom(seed=9000 + seed + i, bytes_lo=64, bytes_hi=bytes_hi) for i in range(n)]
+
+
+def _expected(t, a, b):
+    c = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 0)
+    out = np.zeros(c.out_bytes("all"), np.uint8)
+    c.run_kernel(a, b, iters=1, select="all", out=out)
+    return out
+
+
+def _run(srv, jobs, structs):
+    """Submits every job, waits for all; returns outputs and results."""
+    outs, ids = [], []
+    for (si, key, ab) in jobs:
+        t = structs[si]
+        exp_n = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 0).out_bytes("all")
+        buf = np.zeros(max(exp_n, 1), np.uint8)
+        outs.append(buf)
+        ids.append(srv.submit(t.root_type, t.roots[0], buf.ctypes.data, buf.nbytes, *AB[ab], key=key))
+    res = [srv.wait(i, timeout=120.0) for i in ids]
+    return outs, res
+
+
+def test_alone_equals_mix_equals_oracle(ctx):
+    from paper_1906_01128_amd import dc
+    structs = _structures(8, 1 << 20)
+    schema = dc.Schema(structs[0].types)
+    rng = random.Random(1)
+    jobs = [(rng.randrange(8), 0, rng.randrange(4)) for _ in range(24)]
+    jobs = [(si, (si + 1) if k % 2 == 0 else 0, ab) for k, (si, _, ab) in enumerate(jobs)]
+    # alone: a fresh server per job
+    alone = []
+    for j in jobs:
+        srv = dc.Server(ctx, schema, budget_bytes=1 << 30, max_inflight=4, nstreams=2)
+        o, r = _run(srv, [j], structs)
+        srv.close()
+        alone.append(o[0])
+    # mixed: all submitted at once, structures reused through keys
+    srv = dc.Server(ctx, schema, budget_bytes=1 << 30, max_inflight=6, nstreams=4)
+    mixed, res = _run(srv, jobs, structs)
+    st = srv.stats()
+    srv.close()
+    assert st.completed == len(jobs) and st.reused > 0
+    for k, (j, a, m) in enumerate(zip(jobs, alone, mixed)):
+        want = _expected(structs[j[0]], *AB[j[2]])
+        assert np.array_equal(a, want), f"job {k} alone differs from the oracle"
+        assert np.array_equal(m, want), f"job {k} in the mix differs from the oracle"
+    assert all(r.status == 0 for r in res)
+    assert all(r.t_done >= r.t_admit >= r.t_submit for r in res)
+
+
+def test_budget_admission_and_eviction(ctx):
+    from paper_1906_01128_amd import dc
+    structs = _structures(5, 4 << 20, seed=100)
+    schema = dc.Schema(structs[0].types)
+    sizes = []
+    for t in structs:
+        p = dc.Plan(schema, t.root_type, t.roots)
+        sizes.append(p.arena_bytes + p.scratch_bytes + p.info().out_bytes)
+    budget = max(2 * max(sizes), 8 << 20)
+    srv = dc.Server(ctx, schema, budget_bytes=budget, max_inflight=3, nstreams=2)
+    jobs = [(i % 5, i % 5 + 1, i % 4) for i in range(15)]  # every structure keyed, cycled
+    outs, res = _run(srv, jobs, structs)
+    st = srv.stats()
+    assert st.peak_bytes <= budget
+    assert st.evictions > 0
+    for (si, _, ab), o in zip(jobs, outs):
+        assert np.array_equal(o, _expected(structs[si], *AB[ab]))
+    # a job that can never fit
+    small = dc.Server(ctx, schema, budget_bytes=1 << 20, max_inflight=2, nstreams=1)
+    big = max(range(5), key=lambda i: sizes[i])
+    if sizes[big] > (1 << 20):
+        buf = np.zeros(1 << 24, np.uint8)
+        with pytest.raises(dc.DcError) as e:
+            small.submit(structs[big].root_type, structs[big].roots[0], buf.ctypes.data, buf.nbytes, 1.0, 0.0)
+        assert e.value.name == "BUDGET"
+    small.close()
+    srv.close()

@@ -1,0 +1,135 @@
+"""Host logic of libdc that needs no GPU: the library loads and exports every
+call include/dc.h declares, schemas are validated, and the planner's walk and
+layout agree with the CPU oracle object by object (same order, offsets, sizes)
+and report the same errors."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import fixtures as fx
+import oracle as orc
+from tests.helpers import plan_of, same_objects
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_call():
+    from paper_1906_01128_amd import dc
+    header = open(os.path.join(ROOT, "include", "dc.h")).read()
+    names = set(re.findall(r"^(?:dc_status|const char\*)\s+(dc_\w+)\s*\(", header, re.M))
+    assert len(names) >= 30
+    lib = ctypes.CDLL(dc.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+    # and the binding declares a signature for each
+    bound = set(dc._SIGS) | {"dc_last_error", "dc_version"}
+    assert names <= bound, f"no binding for {sorted(names - bound)}"
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1906_01128_amd import dc
+    monkeypatch.setattr(dc, "_lib", None)
+    monkeypatch.setattr(dc, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        dc.load()
+
+
+def test_schema_validation():
+    from paper_1906_01128_amd import dc
+    s = dc.Schema()
+    ok = s.describe("T", 24, 8, [dict(offset=8, kind="f64", type=0, count_offset=0, count_bytes=8, count_mult=1,
+                                      fixed_count=0)])
+    assert ok == 0
+    bad = [
+        dict(offset=4, kind="f64", type=0, count_offset=0, count_bytes=4, count_mult=1, fixed_count=0),  # misaligned
+        dict(offset=24, kind="f64", type=0, count_offset=0, count_bytes=8, count_mult=1, fixed_count=0),  # outside
+        dict(offset=8, kind="f64", type=0, count_offset=8, count_bytes=8, count_mult=1, fixed_count=0),  # overlaps
+        dict(offset=8, kind="f64", type=0, count_offset=0, count_bytes=2, count_mult=1, fixed_count=0),  # width
+        dict(offset=8, kind=9, type=0, count_offset=0, count_bytes=8, count_mult=1, fixed_count=0),  # kind
+        dict(offset=8, kind="f64", type=0, count_offset=0, count_bytes=8, count_mult=0, fixed_count=0),  # mult
+    ]
+    for f in bad:
+        with pytest.raises(dc.DcError) as e:
+            s.describe("Bad", 24, 8, [f])
+        assert e.value.name == "INVAL"
+
+
+def _compare(t, align=64):
+    p = plan_of(t, align)
+    c = orc.OracleCopy(t.types, t.root_type, t.roots, align, 0)
+    same_objects(p.objects(), c.objects())
+    info = p.info()
+    assert info.arena_bytes == c.arena_bytes == p.arena_bytes
+    assert info.nslots_nonnull == c.nslots
+    assert info.payload_bytes == c.payload_bytes
+    objs = c.objects()
+    leaves = objs[np.isin(objs["kind"], (1, 2))]
+    assert info.leaf_bytes == int(leaves["bytes"].sum())
+    assert info.nleaves == int((leaves["count"] > 0).sum())
+    assert info.out_bytes == c.out_bytes("all")
+    return p, c
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_plan_matches_oracle_random(seed):
+    t = fx.random_tree(500 + seed, max_objects=60, nroots=1 + seed % 4)
+    _compare(t, align=[16, 64, 256, 4096][seed % 4])
+
+
+def test_plan_matches_oracle_workloads():
+    _compare(fx.plain())
+    _compare(fx.linear(n=1000))
+    _compare(fx.linear(k=10, n=100, scheme=0))
+    _compare(fx.dense(q=4, n=50, D=3))
+    _compare(fx.wide(f1=8, f2=16))
+    _compare(fx.md(nsims=50))
+    _compare(fx.broom(seed=3, bytes_hi=1 << 16))
+
+
+def test_plan_segments_cover_many_targets():
+    # more targets than one relocation unit holds, and a struct array with
+    # more slots than a unit takes
+    p, _ = _compare(fx.wide(f1=40, f2=64, lo=1, hi=4))
+    assert p.info().nsegments >= 3
+    p, _ = _compare(fx.plain(nchild=20000, leaf_len=1))
+    assert p.info().nsegments >= 2
+
+
+def test_plan_errors_match_oracle():
+    from paper_1906_01128_amd import dc
+    types = fx.RANDOM_TYPES
+    keep = []
+
+    def mem(n):
+        b = ctypes.create_string_buffer(n)
+        keep.append(b)
+        return ctypes.addressof(b)
+
+    def put(a, off, v, n=8, signed=False):
+        ctypes.memmove(a + off, int(v).to_bytes(n, "little", signed=signed), n)
+
+    p1, p2, v = mem(40), mem(40), mem(32)
+    put(p1, 8, p2)
+    put(p1, 4, 4, 4, True); put(p1, 24, v)
+    put(p2, 4, 3, 4, True); put(p2, 24, v)
+    cases = []
+    cases.append("CONFLICT")
+    for want in ("CONFLICT", "RANGE", "INVAL"):
+        if want == "RANGE":
+            put(p2, 4, 1, 4, True); put(p2, 24, v + 8)
+        if want == "INVAL":
+            put(p2, 24, 0); put(p1, 4, -1, 4, True)
+        with pytest.raises(orc.OracleError) as eo:
+            orc.OracleCopy(types, 0, [p1])
+        with pytest.raises(dc.DcError) as ed:
+            dc.Plan(dc.Schema(types), 0, [p1])
+        assert eo.value.name == ed.value.name == want
+    with pytest.raises(dc.DcError) as ed:
+        dc.Plan(dc.Schema(types), 0, [0])
+    assert ed.value.name == "INVAL"
+    with pytest.raises(dc.DcError) as ed:
+        dc.Plan(dc.Schema(types), 0, [p1], align=8)
+    assert ed.value.name == "INVAL"
