@@ -48,7 +48,7 @@ static std::string tune_key(dc_tree t) {
   };
   char buf[160];
   int dev = 0;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);
   hipDeviceProp_t prop;
   const char* arch = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.gcnArchName : "unknown";
   snprintf(buf, sizeof(buf), "%s/cu%d/seg%d/leaf%d/chunk%d", arch, t->ctx->ncu, bucket(p->segs.size()),
@@ -114,10 +114,12 @@ static dc_status resolve_tune(dc_tree t, const dc_tune* tune, dc_tune* out) {
   return check_tune(*out);
 }
 
-// enqueue the persistent launch (and its counter reset) on s
-static dc_status enqueue_batch(dc_tree t, const LeafArgs& la, const dc_tune& tu, uint32_t flags, hipStream_t s) {
+// enqueue the persistent launch (and its counter reset) on s; under graph
+// capture the tile index must already be built and complete
+static dc_status enqueue_batch(dc_tree t, const LeafArgs& la, const dc_tune& tu, uint32_t flags, hipStream_t s,
+                               bool capturing = false) {
   dc_plan p = t->plan;
-  if (!p->leaves.empty()) DC_TRY(tree_ensure_tiles(t, tu.tile_chunks, s));
+  if (!p->leaves.empty() && !capturing) DC_TRY(tree_ensure_tiles(t, tu.tile_chunks, s));
   hipError_t e = launch_reset_counters(t->tab.hdr, s);
   if (e == hipSuccess) {
     const uint64_t ntiles = p->leaves.empty() ? 0 : ntiles_for(p, tu.tile_chunks);
@@ -191,12 +193,12 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
     if (st != DC_OK) break;
     std::vector<float> ms;
     for (uint32_t r = 0; r < reps && st == DC_OK; r++) {
-      hipEventRecord(e0, s);
+      (void)hipEventRecord(e0, s);
       st = enqueue_batch(t, la, c, flags, s);
-      hipEventRecord(e1, s);
+      (void)hipEventRecord(e1, s);
       if (hipEventSynchronize(e1) != hipSuccess) st = fail(DC_E_HIP, "autotune sync");
       float m = 0;
-      hipEventElapsedTime(&m, e0, e1);
+      (void)hipEventElapsedTime(&m, e0, e1);
       ms.push_back(m);
     }
     if (st != DC_OK) break;
@@ -207,10 +209,10 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
       best = c;
     }
   }
-  hipStreamSynchronize(s);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipStreamDestroy(s);
+  (void)hipStreamSynchronize(s);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
   DC_TRY(st);
   DC_TRY(tree_check(t, nullptr));
   cache_store(tune_key(t), best, best_us);
@@ -255,11 +257,11 @@ dc_status dc_graph_create(dc_tree t, const dc_kernel_args* a, const dc_tune* tun
     return cleanup(fail(DC_E_NOMEM, "pinned image of %llu bytes", (unsigned long long)p->arena_bytes));
   DC_HIP(hipStreamSynchronize(cs));
   DC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  if (upload && p->arena_bytes) hipMemcpyAsync(t->arena, g->up, p->arena_bytes, hipMemcpyHostToDevice, cs);
-  dc_status st = enqueue_batch(t, la, tu, flags, cs);
-  if (download && p->arena_bytes) hipMemcpyAsync(g->down, t->arena, p->arena_bytes, hipMemcpyDeviceToHost, cs);
+  if (upload && p->arena_bytes) (void)hipMemcpyAsync(t->arena, g->up, p->arena_bytes, hipMemcpyHostToDevice, cs);
+  dc_status st = enqueue_batch(t, la, tu, flags, cs, true);
+  if (download && p->arena_bytes) (void)hipMemcpyAsync(g->down, t->arena, p->arena_bytes, hipMemcpyDeviceToHost, cs);
   hipError_t e = hipStreamEndCapture(cs, &g->graph);
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (st != DC_OK) return cleanup(st);
   if (e != hipSuccess) return cleanup(fail(DC_E_HIP, "graph capture: %s", hipGetErrorString(e)));
   e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
@@ -278,11 +280,11 @@ dc_status dc_graph_launch(dc_graph g, void* stream) {
 
 dc_status dc_graph_destroy(dc_graph g) {
   if (!g) return fail(DC_E_INVAL, "dc_graph_destroy: null graph");
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->graph) hipGraphDestroy(g->graph);
-  if (g->up || g->down) hipDeviceSynchronize();
-  if (g->up) hipHostFree(g->up);
-  if (g->down) hipHostFree(g->down);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->up || g->down) (void)hipDeviceSynchronize();
+  if (g->up) (void)hipHostFree(g->up);
+  if (g->down) (void)hipHostFree(g->down);
   delete g;
   return DC_OK;
 }

@@ -219,13 +219,13 @@ dc_status dc_ctx_create(int device, dc_ctx* out) {
 
 dc_status dc_ctx_destroy(dc_ctx c) {
   if (!c) return fail(DC_E_INVAL, "dc_ctx_destroy: null context");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   for (int k = 0; k < dc_ctx_s::kRing; k++) {
-    if (c->pending[k]) hipEventSynchronize(c->ev[k]);
-    if (c->ev[k]) hipEventDestroy(c->ev[k]);
-    if (c->ring[k]) hipHostFree(c->ring[k]);
+    if (c->pending[k]) (void)hipEventSynchronize(c->ev[k]);
+    if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    if (c->ring[k]) (void)hipHostFree(c->ring[k]);
   }
-  if (c->small) hipHostFree(c->small);
+  if (c->small) (void)hipHostFree(c->small);
   delete c->pool;
   delete c;
   return DC_OK;

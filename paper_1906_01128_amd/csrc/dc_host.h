@@ -188,12 +188,16 @@ struct dc_tree_s {
   bool attached = false;
   bool released = false;
   bool paths_uploaded = false;
-  uint32_t tile_T = 0;  // tile size the tile index currently holds
+  uint32_t tile_T = 0;              // tile size the tile index currently holds
+  hipEvent_t tiles_ev = nullptr;    // recorded after the tile index was built
 };
 
 namespace dc {
 dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, const void* const* roots,
                      uint64_t nroots, uint64_t align);
+// Builds the tile index for tiles of T chunks if it holds another size, and
+// makes stream s wait until the index is complete (it may have been built on
+// another stream).
 dc_status tree_ensure_tiles(dc_tree t, uint32_t T, hipStream_t s);
 dc_status tree_check(dc_tree t, hipStream_t s);
 uint64_t ntiles_for(const dc_plan_s* p, uint32_t T);

@@ -12,6 +12,7 @@
 // execute.
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -25,6 +26,8 @@
 #include "dc_host.h"
 
 namespace dc {
+
+constexpr uint32_t kServeTile = 1024;  // the tile size dc_run_kernel uses
 
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -40,7 +43,7 @@ class DevicePool {
     return DC_OK;
   }
   ~DevicePool() {
-    if (base_) hipFree(base_);
+    if (base_) (void)hipFree(base_);
   }
   // returns nullptr when no free range is large enough
   uint8_t* alloc(uint64_t bytes) {
@@ -150,7 +153,7 @@ struct dc_server_s {
     if (r->plan) dc_plan_destroy(r->plan);
     pool.release(r->arena);
     pool.release(r->scratch);
-    if (r->ready) hipEventDestroy(r->ready);
+    if (r->ready) (void)hipEventDestroy(r->ready);
     stats.resident_bytes -= r->bytes;
     delete r;
   }
@@ -240,7 +243,7 @@ dc_status dc_server_s::admit(Job* j, std::unique_lock<std::mutex>& lk) {
       delete r;
       return fail(DC_E_NOMEM, "device pool allocation of %llu bytes", (unsigned long long)need_tree);
     }
-    hipEventCreateWithFlags(&r->ready, hipEventDisableTiming);
+    (void)hipEventCreateWithFlags(&r->ready, hipEventDisableTiming);
     lru.push_front(r);
     r->lru = lru.begin();
     if (r->key) residents[r->key] = r;
@@ -251,6 +254,8 @@ dc_status dc_server_s::admit(Job* j, std::unique_lock<std::mutex>& lk) {
     lk.unlock();
     dc_status st = dc_deep_copy_to_device(issue_ctx, r->plan, r->arena, info.arena_bytes, r->scratch,
                                           info.scratch_bytes, s, &r->tree);
+    // the tile index is part of the resident state that later jobs share
+    if (st == DC_OK) st = tree_ensure_tiles(r->tree, kServeTile, s);
     if (st == DC_OK && hipEventRecord(r->ready, s) != hipSuccess) st = fail(DC_E_HIP, "event record");
     lk.lock();
     if (st != DC_OK) return st;
@@ -289,7 +294,7 @@ dc_status dc_server_s::admit(Job* j, std::unique_lock<std::mutex>& lk) {
 }
 
 void dc_server_s::issue_loop() {
-  hipSetDevice(issue_ctx->device);
+  (void)hipSetDevice(issue_ctx->device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     cv_issue.wait(lk, [&] { return stop || (!pending.empty() && active < cfg.max_inflight); });
@@ -331,7 +336,7 @@ void dc_server_s::issue_loop() {
 }
 
 void dc_server_s::done_loop() {
-  hipSetDevice(done_ctx->device);
+  (void)hipSetDevice(done_ctx->device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     cv_done.wait(lk, [&] { return stop || !inflight.empty(); });
@@ -357,8 +362,17 @@ void dc_server_s::done_loop() {
     std::string err;
     hipStream_t s = dl_stream;
     uint8_t* out = (uint8_t*)j->req.out_host;
+    const dc_plan_s* p = j->res->plan;
+    // only the leaves' bytes go to the caller: bytes between leaves in the
+    // image are never written, as for an out-of-place dc_run_kernel
     st = download(done_ctx, j->d_out, 0, j->out_bytes, s, [&](const uint8_t* buf, uint64_t lo, uint64_t hi) {
-      memcpy(out + lo, buf, hi - lo);
+      size_t l = std::upper_bound(p->leaf_out.begin(), p->leaf_out.end(), lo) - p->leaf_out.begin();
+      if (l > 0) l--;
+      for (; l < p->leaf_out.size() && p->leaf_out[l] < hi; l++) {
+        const uint64_t a = std::max(lo, p->leaf_out[l]);
+        const uint64_t b = std::min<uint64_t>(hi, p->leaf_out[l] + (p->leaf_info[l] & ((1ull << kLeafKindShift) - 1)));
+        if (b > a) memcpy(out + a, buf + (a - lo), b - a);
+      }
     });
     if (st == DC_OK) st = tree_check(j->res->tree, s);
     if (st != DC_OK) err = dc_last_error();
@@ -400,8 +414,8 @@ dc_status dc_server_create(dc_ctx ctx, dc_schema schema, const dc_server_config*
   if (st == DC_OK && hipStreamCreateWithFlags(&s->dl_stream, hipStreamNonBlocking) != hipSuccess)
     st = fail(DC_E_HIP, "stream create");
   if (st != DC_OK) {
-    for (hipStream_t h : s->streams) hipStreamDestroy(h);
-    if (s->dl_stream) hipStreamDestroy(s->dl_stream);
+    for (hipStream_t h : s->streams) (void)hipStreamDestroy(h);
+    if (s->dl_stream) (void)hipStreamDestroy(s->dl_stream);
     if (s->issue_ctx) dc_ctx_destroy(s->issue_ctx);
     if (s->done_ctx) dc_ctx_destroy(s->done_ctx);
     return st;
@@ -469,7 +483,7 @@ dc_status dc_server_wait(dc_server s, uint64_t id, double timeout_s, dc_result* 
   out->out_bytes = j->out_bytes;
   const dc_status st = j->status;
   const std::string err = j->error;
-  if (j->done_ev) hipEventDestroy(j->done_ev);
+  if (j->done_ev) (void)hipEventDestroy(j->done_ev);
   if (j->plan) dc_plan_destroy(j->plan);
   s->jobs.erase(it);
   if (st != DC_OK) return fail(st, "job failed: %s", err.c_str());
@@ -495,19 +509,19 @@ dc_status dc_server_destroy(dc_server s) {
   s->cv_done.notify_all();
   s->issue_thr.join();
   s->done_thr.join();
-  for (hipStream_t h : s->streams) hipStreamSynchronize(h);
-  hipStreamSynchronize(s->dl_stream);
+  for (hipStream_t h : s->streams) (void)hipStreamSynchronize(h);
+  (void)hipStreamSynchronize(s->dl_stream);
   {
     std::lock_guard<std::mutex> lk(s->mu);
     while (!s->lru.empty()) s->free_resident(s->lru.front());
     for (auto& kv : s->jobs) {
-      if (kv.second->done_ev) hipEventDestroy(kv.second->done_ev);
+      if (kv.second->done_ev) (void)hipEventDestroy(kv.second->done_ev);
       if (kv.second->plan) dc_plan_destroy(kv.second->plan);
     }
     s->jobs.clear();
   }
-  for (hipStream_t h : s->streams) hipStreamDestroy(h);
-  hipStreamDestroy(s->dl_stream);
+  for (hipStream_t h : s->streams) (void)hipStreamDestroy(h);
+  (void)hipStreamDestroy(s->dl_stream);
   dc_ctx_destroy(s->issue_ctx);
   dc_ctx_destroy(s->done_ctx);
   delete s;

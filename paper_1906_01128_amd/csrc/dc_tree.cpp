@@ -147,11 +147,16 @@ dc_status tree_check(dc_tree t, hipStream_t s) {
 }
 
 dc_status tree_ensure_tiles(dc_tree t, uint32_t T, hipStream_t s) {
-  if (t->tile_T == T) return DC_OK;
+  if (t->tile_T == T) {
+    if (t->tiles_ev) DC_HIP(hipStreamWaitEvent(s, t->tiles_ev, 0));
+    return DC_OK;
+  }
   if (T < kMinTileChunks || T > kMaxTileChunks || (T & (T - 1))) return fail(DC_E_INVAL, "tile of %u chunks", T);
   if (t->plan->leaves.empty()) return DC_OK;
+  if (!t->tiles_ev) DC_HIP(hipEventCreateWithFlags(&t->tiles_ev, hipEventDisableTiming));
   hipError_t e = launch_tile_index(t->tab, T, ntiles_for(t->plan, T), s);
   if (e != hipSuccess) return fail(DC_E_HIP, "tile index launch: %s", hipGetErrorString(e));
+  DC_HIP(hipEventRecord(t->tiles_ev, s));
   t->tile_T = T;
   return DC_OK;
 }
@@ -430,6 +435,7 @@ dc_status dc_tree_check(dc_tree t, void* stream) {
 dc_status dc_tree_release(dc_tree t) {
   if (!t) return fail(DC_E_INVAL, "dc_tree_release: null tree");
   t->released = true;
+  if (t->tiles_ev) (void)hipEventDestroy(t->tiles_ev);
   delete t;
   return DC_OK;
 }

@@ -90,7 +90,8 @@ def test_budget_admission_and_eviction(ctx):
     small = dc.Server(ctx, schema, budget_bytes=1 << 20, max_inflight=2, nstreams=1)
     big = max(range(5), key=lambda i: sizes[i])
     if sizes[big] > (1 << 20):
-        buf = np.zeros(1 << 24, np.uint8)
+        need = orc.OracleCopy(structs[big].types, structs[big].root_type, structs[big].roots, 64, 0).out_bytes("all")
+        buf = np.zeros(max(need, 1), np.uint8)
         with pytest.raises(dc.DcError) as e:
             small.submit(structs[big].root_type, structs[big].roots[0], buf.ctypes.data, buf.nbytes, 1.0, 0.0)
         assert e.value.name == "BUDGET"
