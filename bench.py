@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="linear", choices=["linear", "wide", "batched", "served"])
+    ap.add_argument("--workload", default="linear", choices=["linear", "wide", "batched", "served", "copycal"])
     ap.add_argument("--passes", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-link", action="store_true", help="skip the host-link measurements")
@@ -380,6 +380,27 @@ def bench_served(args, torch, dc, njobs=200, bytes_hi=64 << 20, rho=0.8, budget=
                        "admitted_while_busy": st.batches, "peak_bytes": st.peak_bytes, "wall_s": round(wall, 3)}}
 
 
+def bench_copycal(args, torch, dc):
+    """A plain device-to-device copy of 1 GiB, three times: the reference
+    kernel whose FETCH_SIZE / WRITE_SIZE counters calibrate the HBM traffic
+    counters of the other kernels (it reads and writes exactly 2^30 bytes)."""
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(3):
+        b.copy_(a)
+    e1.record(s)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / 3
+    return {"metric": "device copy GB/s (counter calibration)", "value": round(2 * n / t / 1e9, 1), "unit": "GB/s",
+            "config": {"workload": "copy 2^30 bytes device to device, 3 times"}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -398,6 +419,8 @@ def main():
         out = bench_wide(args, torch, dc)
     elif args.workload == "batched":
         out = bench_batched(args, torch, dc)
+    elif args.workload == "copycal":
+        out = bench_copycal(args, torch, dc)
     else:
         out = bench_served(args, torch, dc)
     out.setdefault("n_gpus", 1)

@@ -13,16 +13,14 @@
 
 namespace dc {
 
-static const dc_tune kDefaultTune = {256, 4, 1024, 0};
+static const dc_tune kDefaultTune = {256, 4, 16384, 0};
 
 static dc_status check_tune(const dc_tune& t) {
   if (t.block != 256 && t.block != 512 && t.block != 1024) return fail(DC_E_INVAL, "tune.block %u", t.block);
   if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return fail(DC_E_INVAL, "tune.wg_per_cu %u", t.wg_per_cu);
-  if (t.tile_chunks < kMinTileChunks || t.tile_chunks > kMaxTileChunks || (t.tile_chunks & (t.tile_chunks - 1)))
-    return fail(DC_E_INVAL, "tune.tile_chunks %u", t.tile_chunks);
-  const uint32_t u = t.tile_chunks / t.block;
-  if (t.tile_chunks % t.block || (u != 1 && u != 2 && u != 4 && u != 8))
-    return fail(DC_E_INVAL, "tune.tile_chunks / tune.block must be 1, 2, 4 or 8");
+  if (t.tile_chunks < kTileMinChunks || t.tile_chunks > kTileMaxChunks || (t.tile_chunks & (t.tile_chunks - 1)))
+    return fail(DC_E_INVAL, "tune.tile_chunks %u (power of two in %u..%u)", t.tile_chunks, kTileMinChunks,
+                kTileMaxChunks);
   return DC_OK;
 }
 
@@ -122,8 +120,8 @@ static dc_status enqueue_batch(dc_tree t, const LeafArgs& la, const dc_tune& tu,
   if (!p->leaves.empty() && !capturing) DC_TRY(tree_ensure_tiles(t, tu.tile_chunks, s));
   hipError_t e = launch_reset_counters(t->tab.hdr, s);
   if (e == hipSuccess) {
-    const uint64_t ntiles = p->leaves.empty() ? 0 : ntiles_for(p, tu.tile_chunks);
-    e = launch_batch(t->tab, la, flags, tu.block, (uint32_t)t->ctx->ncu * tu.wg_per_cu, tu.tile_chunks, ntiles, s);
+    const uint64_t ntiles = p->leaves.empty() ? 0 : t->ntiles;
+    e = launch_batch(t->tab, la, flags, tu.block, (uint32_t)t->ctx->ncu * tu.wg_per_cu, ntiles, s);
   }
   if (e != hipSuccess) return fail(DC_E_HIP, "batch launch: %s", hipGetErrorString(e));
   return DC_OK;
@@ -179,7 +177,7 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
   const uint32_t flags = DC_BATCH_ATTACH | DC_BATCH_DETACH;
   std::vector<dc_tune> cands;
   for (uint32_t block : {256u, 512u})
-    for (uint32_t tile : {512u, 1024u, 2048u})
+    for (uint32_t tile : {4096u, 16384u, 65536u})
       for (uint32_t wg : {2u, 4u, 8u}) {
         dc_tune c{block, wg, tile, 0};
         if (check_tune(c) == DC_OK) cands.push_back(c);

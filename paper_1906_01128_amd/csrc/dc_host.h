@@ -188,17 +188,21 @@ struct dc_tree_s {
   bool attached = false;
   bool released = false;
   bool paths_uploaded = false;
-  uint32_t tile_T = 0;              // tile size the tile index currently holds
+  uint32_t tile_T = 0;              // tile size of the tile list in scratch
+  uint64_t ntiles = 0;
   hipEvent_t tiles_ev = nullptr;    // recorded after the tile index was built
 };
 
 namespace dc {
 dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, const void* const* roots,
                      uint64_t nroots, uint64_t align);
-// Builds the tile index for tiles of T chunks if it holds another size, and
-// makes stream s wait until the index is complete (it may have been built on
-// another stream).
+// Uploads the tile list for tiles of T chunks if scratch holds another size,
+// and makes stream s wait until that upload is complete (it may have been
+// made on another stream).
 dc_status tree_ensure_tiles(dc_tree t, uint32_t T, hipStream_t s);
 dc_status tree_check(dc_tree t, hipStream_t s);
-uint64_t ntiles_for(const dc_plan_s* p, uint32_t T);
+// The tile list dc_run_kernel uses for every-leaf kernels.
+dc_status tree_prepare_leaf_tiles(dc_tree t, hipStream_t s);
+// Compute tiles of at most T chunks and kTileMaxLeaves leaves, in order.
+std::vector<DevTile> build_tiles(const dc_plan_s* p, uint32_t T);
 }  // namespace dc

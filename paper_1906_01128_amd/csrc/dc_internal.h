@@ -20,14 +20,25 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 // pointer members in ascending offset order) and the distinct objects its
 // non-null slots point to. A workgroup stages those objects' (key -> object)
 // pairs in an LDS hash table and translates every slot of the range.
-constexpr uint32_t kSegMaxTargets = 1024;  // distinct targets per unit
-constexpr uint32_t kSegHashSlots = 2048;   // LDS hash capacity (load <= 1/2)
-constexpr uint32_t kSegMaxSObjs = 512;     // struct objects spanned per unit
-constexpr uint64_t kSegMaxSlots = 16384;   // slots per unit
+constexpr uint32_t kSegMaxTargets = 512;   // distinct targets per unit
+constexpr uint32_t kSegHashSlots = 1024;   // LDS hash capacity (load <= 1/2)
+constexpr uint32_t kSegMaxSObjs = 256;     // struct objects spanned per unit
+constexpr uint64_t kSegMaxSlots = 1024;    // slots per unit
 
-constexpr uint32_t kChunk = 16;            // bytes per vector access of the leaf kernels
-constexpr uint32_t kMinTileChunks = 256;   // smallest compute tile the scratch is sized for
-constexpr uint32_t kMaxTileChunks = 1024;  // largest compute tile (LDS leaf table, 32 KiB)
+constexpr uint32_t kChunk = 16;             // bytes per vector access of the leaf kernels
+
+// Compute tiles: a contiguous range of the 16-byte chunks of the leaves laid
+// end to end, at most kTileMaxLeaves leaves (their table sits in LDS) and at
+// most the requested number of chunks. Built on the host per tile size.
+constexpr uint32_t kTileMinChunks = 1024;     // smallest tile size the scratch is sized for
+constexpr uint32_t kTileMaxChunks = 1u << 20;
+constexpr uint32_t kTileMaxLeaves = 256;
+
+struct DevTile {
+  uint64_t c_lo, c_hi;  // chunk range
+  uint32_t l_lo, l_hi;  // first and last leaf it touches
+  uint64_t pad;
+};
 
 // Struct type as the kernels see it: pointer members sorted by offset.
 struct DevType {
@@ -74,15 +85,20 @@ struct DevHeader {
   uint32_t err_count;
   uint32_t err_code;
   uint64_t err_slot;  // arena offset of the first bad slot
-  // persistent kernel work queue and phase counters
-  uint32_t queue;
-  uint32_t doneA, doneB, doneC;
   uint32_t spin_fail;
   uint32_t pad0;
   // chain resolution result
   uint64_t chain_addr, chain_count;
   uint32_t chain_kind, chain_status;
-  uint64_t pad1[8];
+  uint64_t pad1[4];
+  // persistent kernel work queue and phase counters, one 128-byte cache line
+  // each so that waiting workgroups do not slow the queue down
+  uint32_t queue;
+  uint32_t pad_q[31];
+  uint32_t doneA;
+  uint32_t pad_a[31];
+  uint32_t doneB;
+  uint32_t pad_b[31];
 };
 
 enum DevErr : uint32_t {
@@ -92,13 +108,14 @@ enum DevErr : uint32_t {
   kErrIndex = 3,
   kErrKind = 4,
   kErrSpin = 5,        // persistent kernel wait bound hit
-  kErrWild = 6         // a pointer followed by a kernel lies outside the arena
+  kErrWild = 6,        // a pointer followed by a kernel lies outside the arena
+  kErrChain = 7        // the relocated chain does not lead where the plan says
 };
 
 struct ScratchLayout {
   uint64_t header, types, obj_host, obj_off, sobj, sobj_pre, segs, targets;
   uint64_t leaf_slot, leaf_pre, leaf_info, leaf_out;
-  uint64_t tile_first, paths, hops;
+  uint64_t tiles, paths, hops;
   uint64_t static_end;  // [0, static_end) is uploaded with every deep copy
   uint64_t total;
 };
@@ -119,6 +136,7 @@ struct LeafArgs {
 // and the index to continue at.
 struct ChainArgs {
   uint64_t root_off;
+  uint64_t expect_addr;  // where the plan says the chain ends (0: no check)
   uint32_t nsteps;
   uint32_t pad;
   uint32_t field_off[kMaxChainSteps];
@@ -153,7 +171,7 @@ struct Tables {  // device addresses of the scratch tables
   const uint64_t* leaf_pre;  // nleaves + 1 entries (16-byte chunk prefix)
   const uint64_t* leaf_info;
   const uint64_t* leaf_out;
-  uint32_t* tile_first;
+  const DevTile* tiles;
   const DevPath* paths;
   const uint64_t* hops;
   uint8_t* arena;
@@ -163,16 +181,15 @@ struct Tables {  // device addresses of the scratch tables
 
 hipError_t launch_relocate(const Tables& t, bool attach, hipStream_t s);
 hipError_t launch_resolve_chain(const Tables& t, const ChainArgs& c, hipStream_t s);
-hipError_t launch_tile_index(const Tables& t, uint32_t tile_chunks, uint64_t ntiles, hipStream_t s);
-hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint32_t tile_chunks, uint64_t ntiles,
-                             bool deref_each, hipStream_t s);
-// one FP32/FP64 array whose address the chain resolver left in the header
-hipError_t launch_stream_resolved(const Tables& t, uint64_t count, uint32_t kind, const LeafArgs& la,
+hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint64_t ntiles, bool deref_each, hipStream_t s);
+// one FP32/FP64 array at device address `base`, resolved once before the
+// passes (the pointerchain extraction)
+hipError_t launch_stream_resolved(const Tables& t, uint64_t base, uint64_t count, uint32_t kind, const LeafArgs& la,
                                   hipStream_t s);
 hipError_t launch_stream_deref(const Tables& t, const HopArgs& h, uint64_t count, uint32_t kind,
                                const LeafArgs& la, hipStream_t s);
 hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
-                        uint32_t tile_chunks, uint64_t ntiles, hipStream_t s);
+                        uint64_t ntiles, hipStream_t s);
 hipError_t launch_reset_counters(DevHeader* hdr, hipStream_t s);
 int device_cu_count();
 

@@ -14,15 +14,29 @@ namespace {
 
 constexpr int kRelocBlock = 256;
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Global-memory accesses through addresses held as integers. Without the
+// address-space cast the compiler would emit flat instructions, which also
+// count against the LDS wait counter and cost more to issue.
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
+typedef __attribute__((address_space(1))) double g_double;
+typedef __attribute__((address_space(1))) float g_float;
+typedef __attribute__((address_space(1))) uint64_t g_u64;
+
+__device__ __forceinline__ u32x4 gload16(uint64_t a) { return *(const g_u32x4*)a; }
+__device__ __forceinline__ void gstore16(uint64_t a, u32x4 v) { *(g_u32x4*)a = v; }
+
+
 // LDS of one relocation unit: open-addressing hash of (key -> object) and
 // the slot prefix of the struct arrays the unit spans.
 constexpr size_t kRelocLds = kSegHashSlots * 8 + kSegHashSlots * 4 + (kSegMaxSObjs + 1) * 8;
 
 __device__ __forceinline__ uint32_t hash_slot(uint64_t key) {
   // multiplicative hashing; keys are 16-byte aligned addresses
-  return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - 11)) & (kSegHashSlots - 1);
+  return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - 10)) & (kSegHashSlots - 1);
 }
-static_assert(kSegHashSlots == 2048, "hash_slot assumes 2^11 slots");
+static_assert(kSegHashSlots == 1024, "hash_slot assumes 2^10 slots");
 
 __device__ __forceinline__ void hash_insert(uint64_t* keys, uint32_t* vals, uint64_t key, uint32_t val) {
   uint32_t h = hash_slot(key);
@@ -90,30 +104,41 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
   }
   __syncthreads();
 
-  for (uint64_t j = seg.slot_lo + tid; j < seg.slot_hi; j += bs) {
-    // struct array holding slot j: largest i with pre[i] <= j
-    uint32_t lo = 0, hi = nso;
-    while (hi - lo > 1) {
-      uint32_t mid = (lo + hi) >> 1;
-      if (pre[mid] <= j) lo = mid;
-      else hi = mid;
+  // four slots per thread per round, their loads issued together
+  for (uint64_t jb = seg.slot_lo; jb < seg.slot_hi; jb += 4 * (uint64_t)bs) {
+    uint64_t soff[4], val[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint64_t j = jb + (uint64_t)k * bs + tid;
+      soff[k] = ~0ull;
+      val[k] = 0;
+      if (j >= seg.slot_hi) continue;
+      // struct array holding slot j: largest i with pre[i] <= j
+      uint32_t lo = 0, hi = nso;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= j) lo = mid;
+        else hi = mid;
+      }
+      const DevSObj so = t.sobj[seg.sobj_lo + lo];
+      const DevType* ty = &t.types[so.type];
+      const uint32_t nptr = ty->nptr;
+      const uint64_t local = j - pre[lo];
+      const uint64_t e = local / nptr;
+      const uint32_t f = (uint32_t)(local - e * nptr);
+      soff[k] = so.off + e * ty->size + ty->ptr_off[f];
+      val[k] = *(const g_u64*)(B + soff[k]);
     }
-    const DevSObj so = t.sobj[seg.sobj_lo + lo];
-    const DevType* ty = &t.types[so.type];
-    const uint32_t nptr = ty->nptr;
-    const uint64_t local = j - pre[lo];
-    const uint64_t e = local / nptr;
-    const uint32_t f = (uint32_t)(local - e * nptr);
-    const uint64_t slot_off = so.off + e * ty->size + ty->ptr_off[f];
-    uint64_t* slot = (uint64_t*)(t.arena + slot_off);
-    const uint64_t p = *slot;
-    if (p == 0) continue;
-    const uint32_t obj = hash_find(keys, vals, p);
-    if (obj == kNone) {
-      report_bad_slot(t.hdr, slot_off);
-      continue;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      if (soff[k] == ~0ull || val[k] == 0) continue;
+      const uint32_t obj = hash_find(keys, vals, val[k]);
+      if (obj == kNone) {
+        report_bad_slot(t.hdr, soff[k]);
+        continue;
+      }
+      *(g_u64*)(B + soff[k]) = attach ? B + t.obj_off[obj] : t.obj_host[obj];
     }
-    *slot = attach ? B + t.obj_off[obj] : t.obj_host[obj];
   }
 }
 
@@ -166,6 +191,10 @@ __global__ void k_resolve_chain(Tables t, ChainArgs c) {
         report_wild(h);
         return;
       }
+      if (c.expect_addr && p != c.expect_addr) {
+        atomicAdd(&h->err_count, 1u);
+        atomicCAS(&h->err_code, 0u, (uint32_t)kErrChain);
+      }
       h->chain_addr = p;
       h->chain_count = n;
       h->chain_kind = c.kind[s];
@@ -189,13 +218,14 @@ __global__ void k_resolve_chain(Tables t, ChainArgs c) {
 // ---- leaf arithmetic ------------------------------------------------------------------
 
 union Vec16 {
-  uint4 u;
+  u32x4 u;
   double d[2];
   float f[4];
 };
 
-__device__ __forceinline__ void fma_chunk(Vec16& v, uint32_t kind, const LeafArgs& la) {
-  if (kind == DC_KIND_F64) {
+template <typename T>
+__device__ __forceinline__ void fma_chunk_t(Vec16& v, const LeafArgs& la) {
+  if constexpr (sizeof(T) == 8) {
     v.d[0] = __builtin_fma(v.d[0], la.a, la.b);
     v.d[1] = __builtin_fma(v.d[1], la.a, la.b);
   } else {
@@ -206,15 +236,25 @@ __device__ __forceinline__ void fma_chunk(Vec16& v, uint32_t kind, const LeafArg
   }
 }
 
+// A chunk whose kind differs from lane to lane: both interpretations are
+// computed and the right one kept, so that no lane diverges (the wrong one is
+// discarded; GPU floating point does not trap).
+__device__ __forceinline__ void fma_chunk_any(Vec16& v, bool f64, const LeafArgs& la) {
+  Vec16 d = v, f = v;
+  fma_chunk_t<double>(d, la);
+  fma_chunk_t<float>(f, la);
+  v.u = f64 ? d.u : f.u;
+}
+
 // the first `nbytes` (< 16) bytes of a chunk, element by element
-__device__ __forceinline__ void fma_partial(const uint8_t* src, uint8_t* dst, uint32_t nbytes, uint32_t kind,
+__device__ __forceinline__ void fma_partial(uint64_t src, uint64_t dst, uint32_t nbytes, uint32_t kind,
                                             const LeafArgs& la) {
   if (kind == DC_KIND_F64) {
     for (uint32_t o = 0; o + 8 <= nbytes; o += 8)
-      *(double*)(dst + o) = __builtin_fma(*(const double*)(src + o), la.a, la.b);
+      *(g_double*)(dst + o) = __builtin_fma(*(const g_double*)(src + o), la.a, la.b);
   } else {
     for (uint32_t o = 0; o + 4 <= nbytes; o += 4)
-      *(float*)(dst + o) = __builtin_fmaf(*(const float*)(src + o), la.af, la.bf);
+      *(g_float*)(dst + o) = __builtin_fmaf(*(const g_float*)(src + o), la.af, la.bf);
   }
 }
 
@@ -228,100 +268,109 @@ __device__ __forceinline__ const uint8_t* opaque(const uint8_t* p) {
 
 // ---- one array at the end of a resolved chain ----------------------------------------------
 
-template <int U>
-__global__ void __launch_bounds__(256) k_stream_resolved(Tables t, uint64_t count, uint32_t kind, LeafArgs la) {
-  if (t.hdr->chain_status != 0) return;
-  uint8_t* base = (uint8_t*)t.hdr->chain_addr;  // resolved once, before the region
-  if (!in_arena(t, (uint64_t)base, count * (kind == DC_KIND_F64 ? 8 : 4))) return;  // reported by the resolver
-  const uint8_t* src = la.src_out ? la.out : base;
-  uint8_t* dst = la.out ? la.out : base;
-  const uint32_t es = kind == DC_KIND_F64 ? 8 : 4;
-  const uint64_t bytes = count * es;
-  const uint64_t nfull = bytes / kChunk;
-  const uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x * U + threadIdx.x;
-  Vec16 v[U];
-#pragma unroll
-  for (int k = 0; k < U; k++) {
-    const uint64_t c = c0 + (uint64_t)k * blockDim.x;
-    if (c < nfull) v[k].u = *(const uint4*)(src + c * kChunk);
-  }
-#pragma unroll
-  for (int k = 0; k < U; k++) {
-    const uint64_t c = c0 + (uint64_t)k * blockDim.x;
-    if (c < nfull) {
-      fma_chunk(v[k], kind, la);
-      *(uint4*)(dst + c * kChunk) = v[k].u;
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && nfull * kChunk < bytes)
-    fma_partial(src + nfull * kChunk, dst + nfull * kChunk, (uint32_t)(bytes - nfull * kChunk), kind, la);
-}
-
-// Every element access walks the chain from the root (Section 3: the cost
-// the pointerchain directive removes). U independent elements per thread keep
-// several walks in flight.
 template <int U, typename T>
-__global__ void __launch_bounds__(256) k_stream_deref(Tables t, HopArgs h, uint64_t count, LeafArgs la) {
-  const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x * U + threadIdx.x;
-  const uint8_t* p[U];
-#pragma unroll
-  for (int k = 0; k < U; k++) p[k] = t.arena + h.root_off;
-  bool ok = true;
-  for (uint32_t hop = 0; hop < h.nhops; hop++) {
-    const uint64_t off = h.hop_off[hop];
+__global__ void __launch_bounds__(256) k_stream_resolved(Tables t, uint64_t base, uint64_t count, LeafArgs la) {
+  const uint64_t bytes = count * sizeof(T);
+  if (!in_arena(t, base, bytes)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) report_wild(t.hdr);
+    return;
+  }
+  const uint64_t src = la.src_out ? (uint64_t)la.out : base;
+  const uint64_t dst = la.out ? (uint64_t)la.out : base;
+  const uint64_t nfull = bytes / kChunk;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * U;
+  for (uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x * U + threadIdx.x; c0 < nfull; c0 += stride) {
+    Vec16 v[U];
 #pragma unroll
     for (int k = 0; k < U; k++) {
-      const uint8_t* slot = opaque(p[k]) + off;
-      if (!in_arena(t, (uint64_t)slot, 8)) {
-        ok = false;
-        p[k] = t.arena;
-      } else {
-        p[k] = *(const uint8_t* const*)slot;
+      const uint64_t c = c0 + (uint64_t)k * blockDim.x;
+      if (c < nfull) v[k].u = gload16(src + c * kChunk);
+    }
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+      const uint64_t c = c0 + (uint64_t)k * blockDim.x;
+      if (c < nfull) {
+        fma_chunk_t<T>(v[k], la);
+        gstore16(dst + c * kChunk, v[k].u);
       }
     }
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && nfull * kChunk < bytes)
+    fma_partial(src + nfull * kChunk, dst + nfull * kChunk, (uint32_t)(bytes - nfull * kChunk),
+                sizeof(T) == 8 ? DC_KIND_F64 : DC_KIND_F32, la);
+}
+
+// Reads the pointer at `addr` through the scalar data cache. The chain a
+// wavefront walks is the same for all its lanes, so on CDNA the walk is one
+// scalar load per hop per wavefront, kept apart from the vector caches that the
+// streamed leaf data flows through. The address passes through an opaque
+// register move first, so the compiler can neither hoist the load out of the
+// element loop nor reuse the value of an earlier walk: every element access
+// really reads every pointer of the chain again.
+__device__ __forceinline__ uint64_t walk_load(uint64_t addr) {
+  asm volatile("" : "+s"(addr));
+  return *(const __attribute__((address_space(4))) uint64_t*)addr;
+}
+
+// Every element access walks the chain from the root (Section 3: the cost
+// the pointerchain directive removes). Each thread handles U elements with one
+// walk each; a wavefront's 64 lanes access 64 consecutive elements per walk.
+// The U walks of a wavefront advance hop by hop together, so their scalar
+// loads overlap; the hop offsets (at most MAXH) are held in scalar registers.
+// A slot or leaf outside the arena is replaced by the arena base before it is
+// read, and the wavefront then stops after reporting it.
+template <int U, int MAXH, typename T>
+__global__ void __launch_bounds__(256) k_stream_deref(Tables t, HopArgs h, uint64_t count, LeafArgs la) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t i0 = wave * 64 * U + lane;
+  const uint64_t B = (uint64_t)t.arena, size = t.arena_bytes;
+  uint64_t off[MAXH];
 #pragma unroll
-  for (int k = 0; k < U; k++) ok = ok && in_arena(t, (uint64_t)p[k], count * sizeof(T));
+  for (int j = 0; j < MAXH; j++) off[j] = j < (int)h.nhops ? h.hop_off[j] : 0;
+  uint64_t p[U];
+  bool ok = size >= 8;
+#pragma unroll
+  for (int k = 0; k < U; k++) p[k] = B + h.root_off;
+#pragma unroll
+  for (int j = 0; j < MAXH; j++) {
+    if (j < (int)h.nhops) {
+#pragma unroll
+      for (int k = 0; k < U; k++) {
+        uint64_t slot = p[k] + off[j];
+        const bool in = slot - B <= size - 8;
+        ok = ok && in;
+        slot = in ? slot : B;
+        p[k] = walk_load(slot);
+      }
+    }
+  }
+  const uint64_t need = count * sizeof(T);
+#pragma unroll
+  for (int k = 0; k < U; k++) ok = ok && p[k] - B <= size && need <= size - (p[k] - B);
   if (!ok) {
-    report_wild(t.hdr);
+    if (lane == 0) report_wild(t.hdr);
     return;
   }
   T x[U];
 #pragma unroll
   for (int k = 0; k < U; k++) {
-    const uint64_t i = i0 + (uint64_t)k * blockDim.x;
-    const T* src = la.src_out ? (const T*)la.out : (const T*)p[k];
-    if (i < count) x[k] = src[i];
+    const uint64_t i = i0 + (uint64_t)k * 64;
+    const uint64_t src = la.src_out ? (uint64_t)la.out : p[k];
+    if (i < count) x[k] = *(const __attribute__((address_space(1))) T*)(src + i * sizeof(T));
   }
 #pragma unroll
   for (int k = 0; k < U; k++) {
-    const uint64_t i = i0 + (uint64_t)k * blockDim.x;
-    T* dst = la.out ? (T*)la.out : (T*)p[k];
+    const uint64_t i = i0 + (uint64_t)k * 64;
+    const uint64_t dst = (la.out ? (uint64_t)la.out : p[k]) + i * sizeof(T);
     if (i < count) {
-      if constexpr (sizeof(T) == 8) dst[i] = __builtin_fma(x[k], la.a, la.b);
-      else dst[i] = __builtin_fmaf(x[k], la.af, la.bf);
+      if constexpr (sizeof(T) == 8) *(g_double*)dst = __builtin_fma(x[k], la.a, la.b);
+      else *(g_float*)dst = __builtin_fmaf(x[k], la.af, la.bf);
     }
   }
 }
 
 // ---- every leaf: 16-byte chunks of the concatenated leaves, in tiles ---------------------
-
-__global__ void k_tile_index(Tables t, uint32_t T, uint64_t ntiles) {
-  const uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tile > ntiles) return;
-  if (tile == ntiles) {
-    t.tile_first[tile] = (uint32_t)(t.nleaves - 1);
-    return;
-  }
-  const uint64_t c = tile * T;
-  uint64_t lo = 0, hi = t.nleaves;  // largest l with leaf_pre[l] <= c
-  while (hi - lo > 1) {
-    uint64_t mid = (lo + hi) >> 1;
-    if (t.leaf_pre[mid] <= c) lo = mid;
-    else hi = mid;
-  }
-  t.tile_first[tile] = (uint32_t)lo;
-}
 
 __device__ __forceinline__ uint32_t find_leaf(const uint64_t* pre, uint32_t nl, uint64_t c) {
   uint32_t lo = 0, hi = nl;
@@ -333,19 +382,24 @@ __device__ __forceinline__ uint32_t find_leaf(const uint64_t* pre, uint32_t nl, 
   return lo;
 }
 
-__host__ __device__ constexpr size_t tile_lds_bytes(uint32_t T) { return (size_t)(T + 2) * 4 * 8; }
+// LDS of one compute tile: prefix, address, size|kind and image offset of up
+// to kTileMaxLeaves leaves (and one more prefix entry)
+constexpr size_t kTileLds = (size_t)(kTileMaxLeaves + 2) * 4 * 8;
 
-// One compute tile: chunks [tile*T, tile*T + T) of the leaf concatenation.
-// RESOLVED: each leaf's address is read once per tile from its relocated
-// parent slot. DEREF: each element access walks the leaf's whole path.
+// One compute tile: its chunk range of the leaves laid end to end, processed
+// in rounds of U chunks per thread. RESOLVED: each leaf's address is read
+// once per tile from its relocated parent slot. DEREF: each element access
+// walks the leaf's whole path from its root.
 template <int U, bool DEREF>
-__device__ void leaf_tile(const Tables& t, const LeafArgs& la, uint64_t tile, uint32_t T, uint8_t* lds) {
+__device__ void leaf_tile(const Tables& t, const LeafArgs& la, uint64_t tile, uint8_t* lds) {
+  constexpr uint32_t N = kTileMaxLeaves + 2;
   uint64_t* pre = (uint64_t*)lds;
-  uint64_t* addr = pre + (T + 2);
-  uint64_t* info = addr + (T + 2);
-  uint64_t* outo = info + (T + 2);
+  uint64_t* addr = pre + N;
+  uint64_t* info = addr + N;
+  uint64_t* outo = info + N;
   const int tid = threadIdx.x, bs = blockDim.x;
-  const uint32_t l0 = t.tile_first[tile], l1 = t.tile_first[tile + 1];
+  const DevTile tl = t.tiles[tile];
+  const uint32_t l0 = tl.l_lo, l1 = tl.l_hi;
   const uint32_t nl = l1 - l0 + 1;
   for (uint32_t i = tid; i < nl; i += bs) {
     const uint32_t l = l0 + i;
@@ -353,7 +407,7 @@ __device__ void leaf_tile(const Tables& t, const LeafArgs& la, uint64_t tile, ui
     info[i] = t.leaf_info[l];
     outo[i] = t.leaf_out[l];
     if (!DEREF) {
-      const uint64_t a = *(const uint64_t*)(t.arena + t.leaf_slot[l]);
+      const uint64_t a = *(const g_u64*)((uint64_t)t.arena + t.leaf_slot[l]);
       const uint64_t lb = t.leaf_info[l] & ((1ull << kLeafKindShift) - 1);
       if (in_arena(t, a, lb)) {
         addr[i] = a;
@@ -365,65 +419,71 @@ __device__ void leaf_tile(const Tables& t, const LeafArgs& la, uint64_t tile, ui
   }
   if (tid == 0) pre[nl] = t.leaf_pre[l1 + 1];
   __syncthreads();
-  const uint64_t c_lo = tile * T;
-  const uint64_t c_hi = c_lo + T < t.total_chunks ? c_lo + T : t.total_chunks;
-
-  if (!DEREF) {
-    Vec16 v[U];
-    uint8_t* dst[U];
-    uint32_t nb[U], kd[U];
+  for (uint64_t c_lo = tl.c_lo; c_lo < tl.c_hi; c_lo += (uint64_t)bs * U) {
+    const uint64_t c_hi = tl.c_hi;
+    if (!DEREF) {
+      Vec16 v[U];
+      uint64_t src[U], dst[U];
+      uint32_t nb[U];
+      bool f64[U];
 #pragma unroll
-    for (int k = 0; k < U; k++) {
-      const uint64_t c = c_lo + (uint64_t)k * bs + tid;
-      nb[k] = 0;
-      if (c < c_hi) {
+      for (int k = 0; k < U; k++) {
+        const uint64_t c = c_lo + (uint64_t)k * bs + tid;
+        nb[k] = 0;
+        f64[k] = false;
+        src[k] = dst[k] = 0;
+        if (c < c_hi) {
+          const uint32_t i = find_leaf(pre, nl, c);
+          const uint64_t byte = (c - pre[i]) * kChunk;
+          const uint64_t lb = info[i] & ((1ull << kLeafKindShift) - 1);
+          f64[k] = (info[i] >> kLeafKindShift) == DC_KIND_F64;
+          nb[k] = addr[i] == 0 ? 0 : (uint32_t)(lb - byte < kChunk ? lb - byte : kChunk);
+          src[k] = (la.src_out ? (uint64_t)la.out + outo[i] : addr[i]) + byte;
+          dst[k] = (la.out ? (uint64_t)la.out + outo[i] : addr[i]) + byte;
+        }
+        if (nb[k] == kChunk) v[k].u = gload16(src[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < U; k++) {
+        if (nb[k] == kChunk) {
+          fma_chunk_any(v[k], f64[k], la);
+          gstore16(dst[k], v[k].u);
+        }
+      }
+      // the last, shorter chunk of a leaf, element by element
+#pragma unroll
+      for (int k = 0; k < U; k++)
+        if (nb[k] != 0 && nb[k] != kChunk)
+          fma_partial(src[k], dst[k], nb[k], f64[k] ? DC_KIND_F64 : DC_KIND_F32, la);
+    } else {
+#pragma unroll 1
+      for (int k = 0; k < U; k++) {
+        const uint64_t c = c_lo + (uint64_t)k * bs + tid;
+        if (c >= c_hi) continue;
         const uint32_t i = find_leaf(pre, nl, c);
-        if (addr[i] == 0) continue;
         const uint64_t byte = (c - pre[i]) * kChunk;
         const uint64_t lb = info[i] & ((1ull << kLeafKindShift) - 1);
-        kd[k] = (uint32_t)(info[i] >> kLeafKindShift);
-        nb[k] = (uint32_t)(lb - byte < kChunk ? lb - byte : kChunk);
-        const uint8_t* src = (la.src_out ? la.out + outo[i] : (const uint8_t*)addr[i]) + byte;
-        dst[k] = (la.out ? la.out + outo[i] : (uint8_t*)addr[i]) + byte;
-        if (nb[k] == kChunk) v[k].u = *(const uint4*)src;
-        else fma_partial(src, dst[k], nb[k], kd[k], la);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < U; k++) {
-      if (nb[k] == kChunk) {
-        fma_chunk(v[k], kd[k], la);
-        *(uint4*)dst[k] = v[k].u;
-      }
-    }
-  } else {
-#pragma unroll 1
-    for (int k = 0; k < U; k++) {
-      const uint64_t c = c_lo + (uint64_t)k * bs + tid;
-      if (c >= c_hi) continue;
-      const uint32_t i = find_leaf(pre, nl, c);
-      const uint64_t byte = (c - pre[i]) * kChunk;
-      const uint64_t lb = info[i] & ((1ull << kLeafKindShift) - 1);
-      const uint32_t kind = (uint32_t)(info[i] >> kLeafKindShift);
-      const uint32_t n = (uint32_t)(lb - byte < kChunk ? lb - byte : kChunk);
-      const DevPath path = t.paths[l0 + i];
-      const uint32_t es = kind == DC_KIND_F64 ? 8 : 4;
-      for (uint32_t o = 0; o + es <= n; o += es) {
-        const uint8_t* p = t.arena + path.root_off;
-        bool ok = true;
-        for (uint32_t hp = 0; hp < path.nhops && ok; hp++) {
-          const uint8_t* slot = opaque(p) + t.hops[path.hop_lo + hp];
-          ok = in_arena(t, (uint64_t)slot, 8);
-          if (ok) p = *(const uint8_t* const*)slot;
+        const uint32_t kind = (uint32_t)(info[i] >> kLeafKindShift);
+        const uint32_t n = (uint32_t)(lb - byte < kChunk ? lb - byte : kChunk);
+        const DevPath path = t.paths[l0 + i];
+        const uint32_t es = kind == DC_KIND_F64 ? 8 : 4;
+        for (uint32_t o = 0; o + es <= n; o += es) {
+          const uint8_t* p = t.arena + path.root_off;
+          bool ok = true;
+          for (uint32_t hp = 0; hp < path.nhops && ok; hp++) {
+            const uint8_t* slot = opaque(p) + t.hops[path.hop_lo + hp];
+            ok = in_arena(t, (uint64_t)slot, 8);
+            if (ok) p = (const uint8_t*)*(const g_u64*)(uint64_t)slot;
+          }
+          if (!ok || !in_arena(t, (uint64_t)p, lb)) {
+            report_wild(t.hdr);
+            break;
+          }
+          const uint64_t src = (la.src_out ? (uint64_t)la.out + outo[i] : (uint64_t)p) + byte + o;
+          const uint64_t d = (la.out ? (uint64_t)la.out + outo[i] : (uint64_t)p) + byte + o;
+          if (kind == DC_KIND_F64) *(g_double*)d = __builtin_fma(*(const g_double*)src, la.a, la.b);
+          else *(g_float*)d = __builtin_fmaf(*(const g_float*)src, la.af, la.bf);
         }
-        if (!ok || !in_arena(t, (uint64_t)p, lb)) {
-          report_wild(t.hdr);
-          break;
-        }
-        const uint8_t* src = (la.src_out ? la.out + outo[i] : p) + byte + o;
-        uint8_t* d = (la.out ? la.out + outo[i] : (uint8_t*)p) + byte + o;
-        if (kind == DC_KIND_F64) *(double*)d = __builtin_fma(*(const double*)src, la.a, la.b);
-        else *(float*)d = __builtin_fmaf(*(const float*)src, la.af, la.bf);
       }
     }
   }
@@ -431,19 +491,24 @@ __device__ void leaf_tile(const Tables& t, const LeafArgs& la, uint64_t tile, ui
 }
 
 template <int U, bool DEREF>
-__global__ void __launch_bounds__(256) k_leaf_tiles(Tables t, LeafArgs la, uint32_t T, uint64_t ntiles) {
-  extern __shared__ __align__(16) uint8_t lds[];
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) leaf_tile<U, DEREF>(t, la, tile, T, lds);
+__global__ void __launch_bounds__(256) k_leaf_tiles(Tables t, LeafArgs la, uint64_t ntiles) {
+  __shared__ __align__(16) uint8_t lds[kTileLds];
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) leaf_tile<U, DEREF>(t, la, tile, lds);
 }
 
 // ---- persistent relocate + compute ------------------------------------------------------------
 //
 // One launch, one device work queue. Items: [attach units][compute tile
-// batches][detach units]. A workgroup takes items in queue order; before its
-// first compute item it waits until every attach unit is done (they were all
-// taken earlier, by running workgroups, so the wait ends), and before its
-// first detach unit until every compute batch is done. The waits are bounded:
-// past the bound the kernel records kErrSpin and proceeds, so every wave exits.
+// batches][detach units]. A workgroup takes items in queue order. The
+// compute items read the slots that attach units write, and detach units
+// overwrite slots that compute items read, so a workgroup waits before its
+// first compute item until every attach unit is done and before its first
+// detach unit until every compute item is done. Every item a workgroup waits
+// on was taken earlier by a running workgroup, so the waits end; they are
+// bounded anyway (past the bound the kernel records kErrSpin and proceeds, so
+// every wave exits). A workgroup reports its finished items of a phase once,
+// when it moves past that phase: one device-scope release per workgroup
+// rather than one per item (a release writes back the XCD's L2).
 
 __device__ __forceinline__ uint32_t ld_acquire(uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -453,8 +518,8 @@ __device__ void wait_count(DevHeader* hdr, uint32_t* ctr, uint32_t target) {
   if (threadIdx.x == 0) {
     uint32_t spins = 0;
     while (ld_acquire(ctr) < target) {
-      __builtin_amdgcn_s_sleep(4);
-      if (++spins > (1u << 26)) {
+      __builtin_amdgcn_s_sleep(32);
+      if (++spins > (1u << 24)) {
         atomicCAS(&hdr->err_code, 0u, (uint32_t)kErrSpin);
         atomicAdd(&hdr->spin_fail, 1u);
         break;
@@ -465,16 +530,19 @@ __device__ void wait_count(DevHeader* hdr, uint32_t* ctr, uint32_t target) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
-// every thread releases its own stores at device scope, then one thread
-// counts the item as done
-__device__ __forceinline__ void signal_done(uint32_t* ctr) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+// adds n finished items to a phase counter; release: publish this
+// workgroup's stores (the relocated slots) before the count
+__device__ __forceinline__ void report_done(uint32_t* ctr, uint32_t n, bool release) {
+  if (release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0 && n) {
+    if (release) __hip_atomic_fetch_add(ctr, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_fetch_add(ctr, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 template <int U>
-__global__ void k_batch(Tables t, LeafArgs la, uint32_t flags, uint32_t T, uint64_t ntiles, uint32_t per_item) {
+__global__ void k_batch(Tables t, LeafArgs la, uint32_t flags, uint64_t ntiles, uint32_t per_item) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ uint32_t s_item;
   DevHeader* hdr = t.hdr;
@@ -482,26 +550,33 @@ __global__ void k_batch(Tables t, LeafArgs la, uint32_t flags, uint32_t T, uint6
   const uint32_t nB = (uint32_t)((ntiles + per_item - 1) / per_item);
   const uint32_t nC = (flags & DC_BATCH_DETACH) ? (uint32_t)t.nseg : 0;
   const uint32_t total = nA + nB + nC;
-  bool waitedA = false, waitedB = false;
+  uint32_t myA = 0, myB = 0;  // items finished and not yet reported
+  bool pastA = false, pastB = false, waitedB = false;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(&hdr->queue, 1u);
     __syncthreads();
     const uint32_t item = s_item;
     __syncthreads();
+    if (!pastA && item >= nA) {
+      report_done(&hdr->doneA, myA, true);
+      pastA = true;
+    }
+    if (!pastB && item >= nA + nB) {
+      // compute items only read slots: their count needs no release
+      report_done(&hdr->doneB, myB, false);
+      pastB = true;
+    }
     if (item >= total) break;
     if (item < nA) {
       relocate_unit(t, item, true, lds);
-      signal_done(&hdr->doneA);
+      __syncthreads();
+      myA++;
     } else if (item < nA + nB) {
-      if (!waitedA) {
-        wait_count(hdr, &hdr->doneA, nA);
-        waitedA = true;
-      }
-      const uint64_t b = item - nA;
-      const uint64_t tlo = b * per_item;
+      if (myB == 0) wait_count(hdr, &hdr->doneA, nA);
+      const uint64_t tlo = (uint64_t)(item - nA) * per_item;
       const uint64_t thi = tlo + per_item < ntiles ? tlo + per_item : ntiles;
-      for (uint64_t tile = tlo; tile < thi; tile++) leaf_tile<U, false>(t, la, tile, T, lds);
-      signal_done(&hdr->doneB);
+      for (uint64_t tile = tlo; tile < thi; tile++) leaf_tile<U, false>(t, la, tile, lds);
+      myB++;
     } else {
       if (!waitedB) {
         wait_count(hdr, &hdr->doneB, nB);
@@ -518,7 +593,6 @@ __global__ void k_reset_counters(DevHeader* hdr) {
     hdr->queue = 0;
     hdr->doneA = 0;
     hdr->doneB = 0;
-    hdr->doneC = 0;
   }
 }
 
@@ -543,89 +617,90 @@ hipError_t launch_resolve_chain(const Tables& t, const ChainArgs& c, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_stream_resolved(const Tables& t, uint64_t count, uint32_t kind, const LeafArgs& la,
+hipError_t launch_stream_resolved(const Tables& t, uint64_t base, uint64_t count, uint32_t kind, const LeafArgs& la,
                                   hipStream_t s) {
-  constexpr int U = 4;
+  // An array that fits the 256 MB Infinity Cache streams fastest from a
+  // grid of 16 two-chunk workgroups per compute unit looping over it; a larger
+  // one from one chunk per thread and a grid covering the array.
   const uint64_t bytes = count * (kind == DC_KIND_F64 ? 8 : 4);
   const uint64_t chunks = bytes / kChunk;
-  uint64_t blocks = (chunks + 256ull * U - 1) / (256ull * U);
-  if (blocks == 0) blocks = 1;
-  hipLaunchKernelGGL(k_stream_resolved<U>, dim3((uint32_t)blocks), dim3(256), 0, s, t, count, kind, la);
+  if (bytes <= (192ull << 20)) {
+    constexpr int U = 2;
+    uint64_t blocks = (chunks + 256ull * U - 1) / (256ull * U);
+    const uint64_t cap = (uint64_t)device_cu_count() * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks == 0) blocks = 1;
+    if (kind == DC_KIND_F64)
+      hipLaunchKernelGGL((k_stream_resolved<U, double>), dim3((uint32_t)blocks), dim3(256), 0, s, t, base, count, la);
+    else
+      hipLaunchKernelGGL((k_stream_resolved<U, float>), dim3((uint32_t)blocks), dim3(256), 0, s, t, base, count, la);
+  } else {
+    constexpr int U = 1;
+    uint64_t blocks = (chunks + 256ull * U - 1) / (256ull * U);
+    if (blocks > (1ull << 31) - 1) blocks = (1ull << 31) - 1;
+    if (kind == DC_KIND_F64)
+      hipLaunchKernelGGL((k_stream_resolved<U, double>), dim3((uint32_t)blocks), dim3(256), 0, s, t, base, count, la);
+    else
+      hipLaunchKernelGGL((k_stream_resolved<U, float>), dim3((uint32_t)blocks), dim3(256), 0, s, t, base, count, la);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_stream_deref(const Tables& t, const HopArgs& h, uint64_t count, uint32_t kind,
                                const LeafArgs& la, hipStream_t s) {
   constexpr int U = 4;
-  uint64_t blocks = (count + 256ull * U - 1) / (256ull * U);
+  const uint64_t blocks = (count + 256ull * U - 1) / (256ull * U);
   if (blocks == 0) return hipSuccess;
-  if (kind == DC_KIND_F64)
-    hipLaunchKernelGGL((k_stream_deref<U, double>), dim3((uint32_t)blocks), dim3(256), 0, s, t, h, count, la);
-  else
-    hipLaunchKernelGGL((k_stream_deref<U, float>), dim3((uint32_t)blocks), dim3(256), 0, s, t, h, count, la);
-  return hipGetLastError();
-}
-
-hipError_t launch_tile_index(const Tables& t, uint32_t T, uint64_t ntiles, hipStream_t s) {
-  const uint64_t n = ntiles + 1;
-  hipLaunchKernelGGL(k_tile_index, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, t, T, ntiles);
-  return hipGetLastError();
-}
-
-hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint32_t T, uint64_t ntiles, bool deref_each,
-                             hipStream_t s) {
-  if (ntiles == 0) return hipSuccess;
-  const size_t lds = tile_lds_bytes(T);
-  const uint64_t grid = ntiles < (1u << 20) ? ntiles : (1u << 20);
-  if (T == 1024) {
-    if (deref_each)
-      hipLaunchKernelGGL((k_leaf_tiles<4, true>), dim3((uint32_t)grid), dim3(256), lds, s, t, la, T, ntiles);
-    else
-      hipLaunchKernelGGL((k_leaf_tiles<4, false>), dim3((uint32_t)grid), dim3(256), lds, s, t, la, T, ntiles);
-  } else if (T == 2048) {
-    if (deref_each)
-      hipLaunchKernelGGL((k_leaf_tiles<8, true>), dim3((uint32_t)grid), dim3(256), lds, s, t, la, T, ntiles);
-    else
-      hipLaunchKernelGGL((k_leaf_tiles<8, false>), dim3((uint32_t)grid), dim3(256), lds, s, t, la, T, ntiles);
-  } else if (T == 512) {
-    if (deref_each)
-      hipLaunchKernelGGL((k_leaf_tiles<2, true>), dim3((uint32_t)grid), dim3(256), lds, s, t, la, T, ntiles);
-    else
-      hipLaunchKernelGGL((k_leaf_tiles<2, false>), dim3((uint32_t)grid), dim3(256), lds, s, t, la, T, ntiles);
-  } else if (T == 256) {
-    if (deref_each)
-      hipLaunchKernelGGL((k_leaf_tiles<1, true>), dim3((uint32_t)grid), dim3(256), lds, s, t, la, T, ntiles);
-    else
-      hipLaunchKernelGGL((k_leaf_tiles<1, false>), dim3((uint32_t)grid), dim3(256), lds, s, t, la, T, ntiles);
+  if (h.nhops > kMaxChainSteps) return hipErrorInvalidValue;
+#define DC_DEREF(MAXH)                                                                                     \
+  if (kind == DC_KIND_F64)                                                                                 \
+    hipLaunchKernelGGL((k_stream_deref<U, MAXH, double>), dim3((uint32_t)blocks), dim3(256), 0, s, t, h, count, la); \
+  else                                                                                                     \
+    hipLaunchKernelGGL((k_stream_deref<U, MAXH, float>), dim3((uint32_t)blocks), dim3(256), 0, s, t, h, count, la);
+  if (h.nhops <= 4) {
+    DC_DEREF(4)
+  } else if (h.nhops <= 8) {
+    DC_DEREF(8)
+  } else if (h.nhops <= 16) {
+    DC_DEREF(16)
   } else {
-    return hipErrorInvalidValue;
+    DC_DEREF(32)
   }
+#undef DC_DEREF
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint64_t ntiles, bool deref_each, hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  const uint64_t grid = ntiles < (1u << 20) ? ntiles : (1u << 20);
+  if (deref_each)
+    hipLaunchKernelGGL((k_leaf_tiles<4, true>), dim3((uint32_t)grid), dim3(256), 0, s, t, la, ntiles);
+  else
+    hipLaunchKernelGGL((k_leaf_tiles<4, false>), dim3((uint32_t)grid), dim3(256), 0, s, t, la, ntiles);
   return hipGetLastError();
 }
 
 hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
-                        uint32_t T, uint64_t ntiles, hipStream_t s) {
-  // chunks per thread per tile: T / block, one of 1, 2, 4, 8
-  const uint32_t U = T / block;
-  size_t lds = tile_lds_bytes(T);
-  if (lds < kRelocLds) lds = kRelocLds;
-  // compute tiles are taken in batches so that the queue sees about 16
-  // items per workgroup
-  uint64_t per = ntiles / ((uint64_t)grid * 16 + 1) + 1;
-  const uint32_t per_item = (uint32_t)(per > 64 ? 64 : per);
-#define DC_BATCH_CASE(UU)                                                                                  \
-  case UU:                                                                                                 \
-    hipLaunchKernelGGL(k_batch<UU>, dim3(grid), dim3(block), lds, s, t, la, flags, T, ntiles, per_item); \
-    break;
-  switch (U) {
-    DC_BATCH_CASE(1)
-    DC_BATCH_CASE(2)
-    DC_BATCH_CASE(4)
-    DC_BATCH_CASE(8)
+                        uint64_t ntiles, hipStream_t s) {
+  size_t lds = kTileLds > kRelocLds ? kTileLds : kRelocLds;
+  // compute tiles are taken a few at a time, so that the queue sees about 32
+  // items per workgroup rather than one atomic per tile
+  const uint64_t per = ntiles / ((uint64_t)grid * 32 + 1) + 1;
+  const uint32_t per_item = (uint32_t)(per > 256 ? 256 : per);
+  // chunks per thread per round: 1024 chunks per workgroup round
+  switch (block) {
+    case 256:
+      hipLaunchKernelGGL(k_batch<4>, dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
+      break;
+    case 512:
+      hipLaunchKernelGGL(k_batch<2>, dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
+      break;
+    case 1024:
+      hipLaunchKernelGGL(k_batch<1>, dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
+      break;
     default:
       return hipErrorInvalidValue;
   }
-#undef DC_BATCH_CASE
   return hipGetLastError();
 }
 

@@ -197,7 +197,27 @@ struct Walker {
 };
 }  // namespace
 
-uint64_t ntiles_for(const dc_plan_s* p, uint32_t T) { return (p->total_chunks + T - 1) / T; }
+std::vector<DevTile> build_tiles(const dc_plan_s* p, uint32_t T) {
+  std::vector<DevTile> tiles;
+  const uint64_t nl = p->leaves.size();
+  const uint64_t total = p->total_chunks;
+  uint64_t l = 0;
+  for (uint64_t c = 0; c < total;) {
+    while (p->leaf_pre[l + 1] <= c) l++;  // the leaf holding chunk c
+    uint64_t hi = std::min<uint64_t>(c + T, total);
+    hi = std::min<uint64_t>(hi, p->leaf_pre[std::min<uint64_t>(l + kTileMaxLeaves, nl)]);
+    uint64_t lh = l;
+    while (p->leaf_pre[lh + 1] < hi) lh++;  // the leaf holding chunk hi - 1
+    DevTile tl{};
+    tl.c_lo = c;
+    tl.c_hi = hi;
+    tl.l_lo = (uint32_t)l;
+    tl.l_hi = (uint32_t)lh;
+    tiles.push_back(tl);
+    c = hi;
+  }
+  return tiles;
+}
 
 dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, const void* const* roots,
                      uint64_t nroots, uint64_t align) {
@@ -368,7 +388,9 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     s.leaf_info = take(8 * nl);
     s.leaf_out = take(8 * nl);
     s.static_end = at;
-    s.tile_first = take(4 * (ntiles_for(p, kMinTileChunks) + 2));
+    const uint64_t max_tiles = (p->total_chunks + kTileMinChunks - 1) / kTileMinChunks +
+                               p->leaves.size() / (kTileMaxLeaves - 1) + 2;
+    s.tiles = take(sizeof(DevTile) * max_tiles);
     s.paths = take(sizeof(DevPath) * nl);
     s.hops = take(8 * (p->total_hops + 1));
     s.total = at;

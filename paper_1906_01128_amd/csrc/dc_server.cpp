@@ -27,8 +27,6 @@
 
 namespace dc {
 
-constexpr uint32_t kServeTile = 1024;  // the tile size dc_run_kernel uses
-
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -254,8 +252,8 @@ dc_status dc_server_s::admit(Job* j, std::unique_lock<std::mutex>& lk) {
     lk.unlock();
     dc_status st = dc_deep_copy_to_device(issue_ctx, r->plan, r->arena, info.arena_bytes, r->scratch,
                                           info.scratch_bytes, s, &r->tree);
-    // the tile index is part of the resident state that later jobs share
-    if (st == DC_OK) st = tree_ensure_tiles(r->tree, kServeTile, s);
+    // the tile list is part of the resident state that later jobs share
+    if (st == DC_OK) st = tree_prepare_leaf_tiles(r->tree, s);
     if (st == DC_OK && hipEventRecord(r->ready, s) != hipSuccess) st = fail(DC_E_HIP, "event record");
     lk.lock();
     if (st != DC_OK) return st;

@@ -23,7 +23,7 @@ static Tables make_tables(dc_plan p, uint8_t* arena, uint8_t* scratch) {
   t.leaf_pre = (const uint64_t*)(scratch + s.leaf_pre);
   t.leaf_info = (const uint64_t*)(scratch + s.leaf_info);
   t.leaf_out = (const uint64_t*)(scratch + s.leaf_out);
-  t.tile_first = (uint32_t*)(scratch + s.tile_first);
+  t.tiles = (const DevTile*)(scratch + s.tiles);
   t.paths = (const DevPath*)(scratch + s.paths);
   t.hops = (const uint64_t*)(scratch + s.hops);
   t.arena = arena;
@@ -151,13 +151,17 @@ dc_status tree_ensure_tiles(dc_tree t, uint32_t T, hipStream_t s) {
     if (t->tiles_ev) DC_HIP(hipStreamWaitEvent(s, t->tiles_ev, 0));
     return DC_OK;
   }
-  if (T < kMinTileChunks || T > kMaxTileChunks || (T & (T - 1))) return fail(DC_E_INVAL, "tile of %u chunks", T);
+  if (T < kTileMinChunks || T > kTileMaxChunks || (T & (T - 1))) return fail(DC_E_INVAL, "tile of %u chunks", T);
   if (t->plan->leaves.empty()) return DC_OK;
   if (!t->tiles_ev) DC_HIP(hipEventCreateWithFlags(&t->tiles_ev, hipEventDisableTiming));
-  hipError_t e = launch_tile_index(t->tab, T, ntiles_for(t->plan, T), s);
-  if (e != hipSuccess) return fail(DC_E_HIP, "tile index launch: %s", hipGetErrorString(e));
+  const std::vector<DevTile> tiles = build_tiles(t->plan, T);
+  const uint64_t bytes = sizeof(DevTile) * tiles.size();
+  if (bytes > t->plan->sl.paths - t->plan->sl.tiles) return fail(DC_E_RANGE, "tile list exceeds its scratch space");
+  std::vector<Piece> pcs{{0, tiles.data(), bytes}};
+  DC_TRY(upload_pieces(t->ctx, t->scratch + t->plan->sl.tiles, bytes, pcs, s));
   DC_HIP(hipEventRecord(t->tiles_ev, s));
   t->tile_T = T;
+  t->ntiles = tiles.size();
   return DC_OK;
 }
 
@@ -247,8 +251,20 @@ static dc_status plan_chain(dc_plan p, uint64_t root_index, const dc_step* steps
   return fail(DC_E_INVAL, "empty chain");
 }
 
+// Chunks per tile of the plain every-leaf kernel: the largest power of two
+// (1024..16384) that still gives every compute unit about 16 tiles.
+static uint32_t leaf_tile_for(dc_plan p, int ncu) {
+  uint32_t T = kTileMinChunks;
+  while (T < 16384 && p->total_chunks / (2ull * T) >= 16ull * ncu) T *= 2;
+  return T;
+}
+
 static uint64_t chain_out_bytes(dc_plan p, uint32_t target) {
   return align_up(std::max<uint64_t>(p->objs[target].bytes, 1), p->align);
+}
+
+dc_status tree_prepare_leaf_tiles(dc_tree t, hipStream_t s) {
+  return tree_ensure_tiles(t, leaf_tile_for(t->plan, t->ctx->ncu), s);
 }
 
 }  // namespace dc
@@ -344,11 +360,15 @@ dc_status dc_run_kernel(dc_tree t, const dc_kernel_args* a, void* stream) {
       return fail(DC_E_RANGE, "d_out of %llu bytes, needs %llu", (unsigned long long)a->out_bytes,
                   (unsigned long long)chain_out_bytes(p, cp.target));
     if (a->mode == DC_MODE_RESOLVED) {
-      // resolve once, then every pass indexes the resolved address
+      // Resolve once, before the passes (Section 3): the effective address
+      // comes from the plan, and one walk of the relocated chain on the
+      // device checks that the copy leads there; every pass then indexes it.
+      const uint64_t base = (uint64_t)(uintptr_t)t->arena + o.off;
+      cp.dev.expect_addr = base;
       e = launch_resolve_chain(t->tab, cp.dev, s);
       for (uint32_t it = 0; it < a->iters && e == hipSuccess; it++) {
         la.src_out = (la.out && it > 0) ? 1 : 0;
-        e = launch_stream_resolved(t->tab, o.count, o.kind, la, s);
+        e = launch_stream_resolved(t->tab, base, o.count, o.kind, la, s);
       }
     } else {
       for (uint32_t it = 0; it < a->iters && e == hipSuccess; it++) {
@@ -361,13 +381,12 @@ dc_status dc_run_kernel(dc_tree t, const dc_kernel_args* a, void* stream) {
       return fail(DC_E_RANGE, "d_out of %llu bytes, needs %llu", (unsigned long long)a->out_bytes,
                   (unsigned long long)p->out_bytes);
     if (p->leaves.empty() || a->iters == 0) return DC_OK;
-    const uint32_t T = 1024;
-    DC_TRY(tree_ensure_tiles(t, T, s));
+    DC_TRY(tree_ensure_tiles(t, leaf_tile_for(p, t->ctx->ncu), s));
     const bool deref = a->mode == DC_MODE_DEREF_EACH;
     if (deref) DC_TRY(ensure_paths(t, s));
     for (uint32_t it = 0; it < a->iters && e == hipSuccess; it++) {
       la.src_out = (la.out && it > 0) ? 1 : 0;
-      e = launch_leaf_tiles(t->tab, la, T, ntiles_for(p, T), deref, s);
+      e = launch_leaf_tiles(t->tab, la, t->ntiles, deref, s);
     }
   }
   if (e != hipSuccess) return fail(DC_E_HIP, "kernel launch: %s", hipGetErrorString(e));

@@ -40,10 +40,10 @@ def test_batch_md_attach(ctx):
     assert c.tree.resolve_chain([(0, 3), (2, 0)], root_index=7) == c.oracle.resolve_chain(7, [(0, 3), (2, 0)])
 
 
-@pytest.mark.parametrize("tune", [None, dict(block=256, wg_per_cu=2, tile_chunks=256),
-                                  dict(block=512, wg_per_cu=8, tile_chunks=1024),
-                                  dict(block=1024, wg_per_cu=1, tile_chunks=1024),
-                                  dict(block=256, wg_per_cu=4, tile_chunks=512)])
+@pytest.mark.parametrize("tune", [None, dict(block=256, wg_per_cu=2, tile_chunks=1024),
+                                  dict(block=512, wg_per_cu=8, tile_chunks=4096),
+                                  dict(block=1024, wg_per_cu=1, tile_chunks=65536),
+                                  dict(block=256, wg_per_cu=4, tile_chunks=1 << 20)])
 def test_batch_attach_detach_any_tile_shape(ctx, tune):
     t = fx.md(seed=5, nsims=60, cells_lo=1, cells_hi=40, mean_atoms=5)
     c = Copy(ctx, t, relocate=False)
