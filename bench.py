@@ -312,6 +312,21 @@ def bench_batched(args, torch, dc):
     torch.cuda.synchronize()
     tree.check()
     step_s = [a.elapsed_time(b) / 1e3 for a, b in recs]
+    # the same work as separate launches: attach, one pass over every leaf, detach
+    phases = {"attach": [], "leaf_tiles": [], "detach": []}
+    for _ in range(3):
+        e = [ev() for _ in range(4)]
+        e[0].record(s)
+        tree.attach()
+        e[1].record(s)
+        tree.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.5)
+        e[2].record(s)
+        tree.detach()
+        e[3].record(s)
+        torch.cuda.synchronize()
+        for k, name in enumerate(("attach", "leaf_tiles", "detach")):
+            phases[name].append(e[k].elapsed_time(e[k + 1]))
+    tree.check()
     kb = 2 * info.leaf_bytes
     rb = 2 * (info.nslots_nonnull * 16 + info.nslots * 8 + info.nobjects * 16)
     v = (kb + rb) / pct(step_s, 50) / 1e9
@@ -325,6 +340,7 @@ def bench_batched(args, torch, dc):
             "roofline": {"bound": "hbm", "kernel": "k_batch", "achieved": round(v, 1), "peak": HBM_PEAK_GBPS,
                          "unit": "GB/s", "frac": round(v / HBM_PEAK_GBPS, 4), "traffic": None},
             "latency_ms": {"p50": round(1e3 * pct(step_s, 50), 3), "p99": round(1e3 * pct(step_s, 99), 3)},
+            "separate_launches_ms": {k: round(pct(v_, 50), 3) for k, v_ in phases.items()},
             "host": {"plan_s": round(plan_s, 3), "stage_s": round(stage_s, 3),
                      "stage_GBps": round(plan.arena_bytes / stage_s / 1e9, 2)}}
 

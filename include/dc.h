@@ -155,6 +155,17 @@ dc_status dc_schema_describe(dc_schema schema, const char* name, uint32_t size, 
  * (a pointer into the middle of another array). */
 dc_status dc_plan_create(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* const* roots, uint64_t nroots,
                          uint64_t align, dc_plan* out, uint64_t* arena_bytes, uint64_t* scratch_bytes);
+/* Selective (partial) deep copy (Section 2): only the pointer members a
+ * kernel needs are followed. follow[t] (t < nfollow) has bit i set when
+ * pointer field i of type t (its position in the field list given to
+ * dc_schema_describe) is followed; types at or past nfollow follow every
+ * field. An unfollowed member is not walked, its array is not copied, and it
+ * reads as NULL in the device copy. Otherwise as dc_plan_create.
+ * Errors: DC_E_INVAL also for nfollow above the number of types or a mask
+ * with a bit past its type's field count. */
+dc_status dc_plan_create_selective(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* const* roots,
+                                   uint64_t nroots, uint64_t align, const uint32_t* follow, uint32_t nfollow,
+                                   dc_plan* out, uint64_t* arena_bytes, uint64_t* scratch_bytes);
 dc_status dc_plan_destroy(dc_plan plan);
 dc_status dc_plan_query(dc_plan plan, dc_plan_info* out);
 /* Copies up to cap placed objects, in arena order, into out; *n receives the
@@ -197,6 +208,26 @@ dc_status dc_detach(dc_tree tree, void* stream);
  * step, index past the array), DC_E_STATE (not attached). */
 dc_status dc_resolve_chain(dc_tree tree, uint64_t root_index, const dc_step* steps, uint32_t nsteps, void* stream,
                            dc_chain* out);
+
+/* The pointerchain transfer scheme (Section 3): resolve a chain on the host
+ * tree and transfer only the array it ends in; the structures along the
+ * chain are not copied, since the kernel needs only the effective address.
+ * dc_chain_to_device walks the chain from the host struct `root` (type
+ * root_type) and copies the final array (count * element size bytes) into
+ * d_buf (a 16-byte aligned device buffer of buf_bytes); *out receives d_buf,
+ * the count and the kind. Returns once the host array has been read.
+ * Errors: DC_E_INVAL (bad field or steps), DC_E_RANGE (null before the end,
+ * index past an array, buffer too small). */
+dc_status dc_chain_to_device(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* root, const dc_step* steps,
+                             uint32_t nsteps, void* d_buf, uint64_t buf_bytes, void* stream, dc_chain* out);
+/* `iters` passes of x = fma(x, a, b) (FP64: a, b; FP32: af, bf) over an array
+ * placed by dc_chain_to_device. Asynchronous on `stream`. */
+dc_status dc_chain_run_kernel(dc_ctx ctx, const dc_chain* c, uint32_t iters, double a, double b, float af, float bf,
+                              void* stream);
+/* Transfers such an array back into the host array the same chain ends in.
+ * Returns when the host array is updated. */
+dc_status dc_chain_copy_back(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* root, const dc_step* steps,
+                             uint32_t nsteps, const dc_chain* c, void* stream);
 
 /* ---- leaf kernels (Algorithm 2 step 4) --------------------------------------------- */
 

@@ -63,6 +63,9 @@ def _load():
         lib.or_deep_copy.argtypes = [ctypes.POINTER(_Type), u32, u32, ctypes.POINTER(vp), u64, u64, u64,
                                      ctypes.POINTER(vp)]
         lib.or_deep_copy.restype = ctypes.c_int
+        lib.or_deep_copy_selective.argtypes = [ctypes.POINTER(_Type), u32, u32, ctypes.POINTER(vp), u64, u64, u64,
+                                               ctypes.POINTER(u32), ctypes.POINTER(vp)]
+        lib.or_deep_copy_selective.restype = ctypes.c_int
         lib.or_free.argtypes = [vp]
         lib.or_free.restype = None
         lib.or_arena.argtypes = [vp]
@@ -120,13 +123,20 @@ def _chain_arrays(chain):
 class OracleCopy:
     """The oracle's deep copy of a host tree, laid out as if at address `base`."""
 
-    def __init__(self, types, root_type, roots, align=64, base=0):
+    def __init__(self, types, root_type, roots, align=64, base=0, follow=None):
+        """follow: None (every pointer member) or one bitmask per type over
+        its field list (selective deep copy)."""
         lib = _load()
         self._types = make_types(types)
         self._roots = (ctypes.c_void_p * max(1, len(roots)))(*roots)
         h = ctypes.c_void_p()
-        rc = lib.or_deep_copy(self._types, len(types), root_type, self._roots, len(roots), align, base,
-                              ctypes.byref(h))
+        if follow is None:
+            rc = lib.or_deep_copy(self._types, len(types), root_type, self._roots, len(roots), align, base,
+                                  ctypes.byref(h))
+        else:
+            fm = (ctypes.c_uint32 * len(types))(*follow)
+            rc = lib.or_deep_copy_selective(self._types, len(types), root_type, self._roots, len(roots), align,
+                                            base, fm, ctypes.byref(h))
         if rc:
             raise OracleError(rc, "or_deep_copy")
         self._h = h

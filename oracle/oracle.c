@@ -9,6 +9,7 @@
 struct or_copy {
   const or_type* types; /* copied */
   uint32_t ntypes;
+  uint32_t* follow;     /* per type: fields to follow (bit per field) */
   uint64_t align, base;
   void* const* roots;
   uint64_t nroots;
@@ -153,6 +154,7 @@ static int visit(or_copy* c, uint64_t idx) {
   for (uint64_t e = 0; e < o.count; e++) {
     const uint8_t* elem = (const uint8_t*)(uintptr_t)o.host + e * t->size;
     for (uint32_t k = 0; k < t->nfields; k++) {
+      if (!((c->follow[o.type] >> order[k]) & 1u)) continue;
       const or_field* f = &t->fields[order[k]];
       uint64_t p;
       memcpy(&p, elem + f->offset, 8);
@@ -205,6 +207,11 @@ static int check_no_overlap(const or_copy* c) {
 
 int or_deep_copy(const or_type* types, uint32_t ntypes, uint32_t root_type, void* const* roots, uint64_t nroots,
                  uint64_t align, uint64_t base, or_copy** out) {
+  return or_deep_copy_selective(types, ntypes, root_type, roots, nroots, align, base, NULL, out);
+}
+
+int or_deep_copy_selective(const or_type* types, uint32_t ntypes, uint32_t root_type, void* const* roots,
+                           uint64_t nroots, uint64_t align, uint64_t base, const uint32_t* follow, or_copy** out) {
   *out = NULL;
   if (!types || ntypes == 0 || root_type >= ntypes || (!roots && nroots)) return OR_E_INVAL;
   if (align == 0 || (align & (align - 1))) return OR_E_INVAL;
@@ -229,6 +236,12 @@ int or_deep_copy(const or_type* types, uint32_t ntypes, uint32_t root_type, void
   }
   memcpy(tcopy, types, ntypes * sizeof(or_type));
   c->types = tcopy;
+  c->follow = (uint32_t*)malloc(ntypes * sizeof(uint32_t));
+  if (!c->follow) {
+    or_free(c);
+    return OR_E_NOMEM;
+  }
+  for (uint32_t i = 0; i < ntypes; i++) c->follow[i] = follow ? follow[i] : 0xFFFFFFFFu;
   c->ntypes = ntypes;
   c->mask = 63;
   c->align = align;
@@ -292,6 +305,11 @@ int or_deep_copy(const or_type* types, uint32_t ntypes, uint32_t root_type, void
         uint64_t p;
         memcpy(&p, elem + t->fields[k].offset, 8);
         if (p == 0) continue;
+        if (!((c->follow[o->type] >> k) & 1u)) {
+          /* an unfollowed member reads as null in the copy */
+          memset(elem + t->fields[k].offset, 0, 8);
+          continue;
+        }
         int64_t j = map_find(c, p);
         if (j < 0) {
           or_free(c);
@@ -310,6 +328,7 @@ int or_deep_copy(const or_type* types, uint32_t ntypes, uint32_t root_type, void
 void or_free(or_copy* c) {
   if (!c) return;
   free((void*)c->types);
+  free(c->follow);
   free(c->root_obj);
   free(c->objs);
   free(c->keys);

@@ -67,6 +67,12 @@ typedef struct or_copy or_copy;
  * as if the buffer lived at address `base`. */
 int or_deep_copy(const or_type* types, uint32_t ntypes, uint32_t root_type, void* const* roots, uint64_t nroots,
                  uint64_t align, uint64_t base, or_copy** out);
+/* Selective deep copy (Section 2, selective or partial deep copy): follow[t]
+ * has bit i set when pointer field i (position in type t's field list) is to
+ * be followed. An unfollowed field is not walked, its array is not copied,
+ * and it reads as a null pointer in the buffer. follow == NULL follows all. */
+int or_deep_copy_selective(const or_type* types, uint32_t ntypes, uint32_t root_type, void* const* roots,
+                           uint64_t nroots, uint64_t align, uint64_t base, const uint32_t* follow, or_copy** out);
 void or_free(or_copy* c);
 
 uint8_t* or_arena(const or_copy* c);

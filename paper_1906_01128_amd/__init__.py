@@ -5,4 +5,4 @@ The compute path is libdc.so (hand-written HIP for gfx950); `dc` is its
 ctypes binding. Importing `dc` fails if the library has not been built.
 """
 from . import dc  # noqa: F401
-from .dc import (Context, DcError, Graph, Plan, Schema, Server, Tree, load, version)  # noqa: F401
+from .dc import (ChainCopy, Context, DcError, Graph, Plan, Schema, Server, Tree, load, version)  # noqa: F401

@@ -85,7 +85,7 @@ void Pool::run(int n, const std::function<void(int)>& fn) {
 // Writes destination range [lo, hi) into buf: the bytes of every piece that
 // overlaps it, zeros elsewhere. Split across the pool in ~4 MiB parts.
 static void pack_range(dc_ctx ctx, uint8_t* buf, uint64_t lo, uint64_t hi, const PieceSource& src) {
-  const uint64_t part = 4ull << 20;
+  const uint64_t part = 1ull << 20;
   const int nparts = (int)((hi - lo + part - 1) / part);
   ctx->pool->run(nparts, [&](int k) {
     const uint64_t plo = lo + (uint64_t)k * part;
@@ -210,6 +210,11 @@ dc_status dc_ctx_create(int device, dc_ctx* out) {
     dc_ctx_destroy(c);
     return fail(DC_E_NOMEM, "dc_ctx_create: pinned result buffer");
   }
+  if (hipMalloc((void**)&c->dev_hdr, sizeof(DevHeader)) != hipSuccess ||
+      hipMemset(c->dev_hdr, 0, sizeof(DevHeader)) != hipSuccess) {
+    dc_ctx_destroy(c);
+    return fail(DC_E_NOMEM, "dc_ctx_create: device header");
+  }
   unsigned hw = std::thread::hardware_concurrency();
   c->pool = new Pool((int)std::max(1u, std::min(hw ? hw : 1u, 32u)));
   *out = c;
@@ -226,6 +231,7 @@ dc_status dc_ctx_destroy(dc_ctx c) {
     if (c->ring[k]) (void)hipHostFree(c->ring[k]);
   }
   if (c->small) (void)hipHostFree(c->small);
+  if (c->dev_hdr) (void)hipFree(c->dev_hdr);
   delete c->pool;
   delete c;
   return DC_OK;

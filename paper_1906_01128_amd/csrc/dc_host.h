@@ -73,13 +73,16 @@ struct dc_ctx_impl;
 struct dc_ctx_s {
   int device = 0;
   int ncu = 256;
-  static constexpr int kRing = 4;
-  uint64_t chunk_bytes = 64ull << 20;
+  // pinned staging: 8 chunks of 16 MiB, so that packing one chunk overlaps
+  // the transfer of the previous ones even for transfers of ~100 MB
+  static constexpr int kRing = 8;
+  uint64_t chunk_bytes = 16ull << 20;
   uint8_t* ring[kRing] = {};
   hipEvent_t ev[kRing] = {};
   bool pending[kRing] = {};
   int next = 0;
   uint8_t* small = nullptr;  // pinned scratch for header reads
+  dc::DevHeader* dev_hdr = nullptr;  // device header for kernels outside a tree
   dc::Pool* pool = nullptr;
 };
 
@@ -113,6 +116,7 @@ struct TypeDesc {
   std::vector<uint32_t> order;    // field indices by ascending offset
   std::vector<uint32_t> pos;      // position of field i in `order`
   std::vector<std::pair<uint32_t, uint32_t>> plain_runs;  // [lo, hi) byte runs that are not pointers
+  uint32_t follow = 0xFFFFFFFFu;  // per field (list order): followed by the walk
 };
 
 }  // namespace dc
@@ -195,7 +199,7 @@ struct dc_tree_s {
 
 namespace dc {
 dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, const void* const* roots,
-                     uint64_t nroots, uint64_t align);
+                     uint64_t nroots, uint64_t align, const uint32_t* follow = nullptr, uint32_t nfollow = 0);
 // Uploads the tile list for tiles of T chunks if scratch holds another size,
 // and makes stream s wait until that upload is complete (it may have been
 // made on another stream).

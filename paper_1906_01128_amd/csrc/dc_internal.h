@@ -44,6 +44,8 @@ struct DevTile {
 struct DevType {
   uint32_t size;
   uint32_t nptr;
+  uint32_t follow;  // bit k: pointer member k (offset order) is followed
+  uint32_t pad;
   uint32_t ptr_off[kMaxFields];
   uint32_t kind[kMaxFields];
   uint32_t ptype[kMaxFields];

@@ -128,6 +128,11 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
       const uint32_t f = (uint32_t)(local - e * nptr);
       soff[k] = so.off + e * ty->size + ty->ptr_off[f];
       val[k] = *(const g_u64*)(B + soff[k]);
+      // a member left out of a selective copy reads as null on the device
+      if (!((ty->follow >> f) & 1u)) {
+        if (val[k] != 0) *(g_u64*)(B + soff[k]) = 0;
+        val[k] = 0;
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; k++) {

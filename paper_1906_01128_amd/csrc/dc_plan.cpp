@@ -160,7 +160,8 @@ struct Walker {
         continue;
       }
       const uint32_t nptr = (uint32_t)t.order.size();
-      const dc_field& fd = t.fields[t.order[fr.k]];
+      const uint32_t fi = t.order[fr.k];
+      const dc_field& fd = t.fields[fi];
       const uint8_t* elem = (const uint8_t*)(uintptr_t)o.host + fr.e * t.size;
       const uint64_t slot = p->sobj_pre[o.sobj] + fr.e * nptr + fr.k;
       const uint64_t rel = fr.e * t.size + fd.offset;
@@ -169,6 +170,7 @@ struct Walker {
         fr.k = 0;
         fr.e++;
       }
+      if (!((t.follow >> fi) & 1u)) continue;  // not part of a selective copy
       uint64_t ptr;
       memcpy(&ptr, elem + fd.offset, 8);
       if (ptr == 0) continue;
@@ -220,8 +222,15 @@ std::vector<DevTile> build_tiles(const dc_plan_s* p, uint32_t T) {
 }
 
 dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, const void* const* roots,
-                     uint64_t nroots, uint64_t align) {
+                     uint64_t nroots, uint64_t align, const uint32_t* follow, uint32_t nfollow) {
   p->types = schema->types;
+  if (nfollow > p->types.size()) return fail(DC_E_INVAL, "%u follow masks for %zu types", nfollow, p->types.size());
+  for (uint32_t i = 0; i < nfollow; i++) {
+    const size_t nf = p->types[i].fields.size();
+    if (nf < 32 && (follow[i] >> nf) != 0)
+      return fail(DC_E_INVAL, "follow mask 0x%x of type %u sets bits past its %zu fields", follow[i], i, nf);
+    p->types[i].follow = follow[i];
+  }
   if (root_type >= p->types.size()) return fail(DC_E_INVAL, "root type %u not described", root_type);
   for (size_t i = 0; i < p->types.size(); i++)
     for (const dc_field& f : p->types[i].fields)
@@ -354,6 +363,7 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     d.size = t.size;
     d.nptr = (uint32_t)t.order.size();
     for (uint32_t k = 0; k < d.nptr; k++) {
+      if ((t.follow >> t.order[k]) & 1u) d.follow |= 1u << k;
       const dc_field& f = t.fields[t.order[k]];
       d.ptr_off[k] = f.offset;
       d.kind[k] = f.kind;
@@ -406,7 +416,15 @@ extern "C" {
 
 dc_status dc_plan_create(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* const* roots, uint64_t nroots,
                          uint64_t align, dc_plan* out, uint64_t* arena_bytes, uint64_t* scratch_bytes) {
+  return dc_plan_create_selective(ctx, schema, root_type, roots, nroots, align, nullptr, 0, out, arena_bytes,
+                                  scratch_bytes);
+}
+
+dc_status dc_plan_create_selective(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* const* roots,
+                                   uint64_t nroots, uint64_t align, const uint32_t* follow, uint32_t nfollow,
+                                   dc_plan* out, uint64_t* arena_bytes, uint64_t* scratch_bytes) {
   (void)ctx;
+  if (nfollow && !follow) return fail(DC_E_INVAL, "dc_plan_create_selective: null follow masks");
   if (!out) return fail(DC_E_INVAL, "dc_plan_create: out is null");
   *out = nullptr;
   if (!schema || (!roots && nroots)) return fail(DC_E_INVAL, "dc_plan_create: null schema or roots");
@@ -414,7 +432,7 @@ dc_status dc_plan_create(dc_ctx ctx, dc_schema schema, uint32_t root_type, const
   if (align < 16 || align > 4096 || (align & (align - 1)))
     return fail(DC_E_INVAL, "dc_plan_create: align %llu (power of two in 16..4096)", (unsigned long long)align);
   dc_plan p = new dc_plan_s();
-  dc_status st = plan_build(p, schema, root_type, roots, nroots, align);
+  dc_status st = plan_build(p, schema, root_type, roots, nroots, align, follow, nfollow);
   if (st != DC_OK) {
     delete p;
     return st;

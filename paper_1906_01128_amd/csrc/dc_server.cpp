@@ -364,13 +364,21 @@ void dc_server_s::done_loop() {
     // only the leaves' bytes go to the caller: bytes between leaves in the
     // image are never written, as for an out-of-place dc_run_kernel
     st = download(done_ctx, j->d_out, 0, j->out_bytes, s, [&](const uint8_t* buf, uint64_t lo, uint64_t hi) {
-      size_t l = std::upper_bound(p->leaf_out.begin(), p->leaf_out.end(), lo) - p->leaf_out.begin();
-      if (l > 0) l--;
-      for (; l < p->leaf_out.size() && p->leaf_out[l] < hi; l++) {
-        const uint64_t a = std::max(lo, p->leaf_out[l]);
-        const uint64_t b = std::min<uint64_t>(hi, p->leaf_out[l] + (p->leaf_info[l] & ((1ull << kLeafKindShift) - 1)));
-        if (b > a) memcpy(out + a, buf + (a - lo), b - a);
-      }
+      // split the chunk among the pool's threads; each copies the leaf
+      // bytes that fall in its part
+      const uint64_t part = 1ull << 20;
+      const int nparts = (int)((hi - lo + part - 1) / part);
+      done_ctx->pool->run(nparts, [&](int k) {
+        const uint64_t plo = lo + (uint64_t)k * part, phi = std::min(hi, plo + part);
+        size_t l = std::upper_bound(p->leaf_out.begin(), p->leaf_out.end(), plo) - p->leaf_out.begin();
+        if (l > 0) l--;
+        for (; l < p->leaf_out.size() && p->leaf_out[l] < phi; l++) {
+          const uint64_t a = std::max(plo, p->leaf_out[l]);
+          const uint64_t b =
+              std::min<uint64_t>(phi, p->leaf_out[l] + (p->leaf_info[l] & ((1ull << kLeafKindShift) - 1)));
+          if (b > a) memcpy(out + a, buf + (a - lo), b - a);
+        }
+      });
     });
     if (st == DC_OK) st = tree_check(j->res->tree, s);
     if (st != DC_OK) err = dc_last_error();

@@ -412,7 +412,7 @@ dc_status dc_copy_back(dc_tree t, uint32_t flags, void* stream) {
     const PieceSource src = arena_source(p);
     Pool* pool = t->ctx->pool;
     dc_status st = download(t->ctx, t->arena, lo, hi, s, [&](const uint8_t* buf, uint64_t clo, uint64_t chi) {
-      const uint64_t part = 4ull << 20;
+      const uint64_t part = 1ull << 20;
       const int nparts = (int)((chi - clo + part - 1) / part);
       pool->run(nparts, [&](int k) {
         const uint64_t plo = clo + (uint64_t)k * part, phi = std::min(chi, plo + part);

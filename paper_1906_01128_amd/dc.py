@@ -101,6 +101,8 @@ _SIGS = {
     "dc_schema_describe": [vp, ctypes.c_char_p, u32, u32, ctypes.POINTER(Field), u32, ctypes.POINTER(u32)],
     "dc_plan_create": [vp, vp, u32, ctypes.POINTER(vp), u64, u64, ctypes.POINTER(vp), ctypes.POINTER(u64),
                        ctypes.POINTER(u64)],
+    "dc_plan_create_selective": [vp, vp, u32, ctypes.POINTER(vp), u64, u64, ctypes.POINTER(u32), u32,
+                                 ctypes.POINTER(vp), ctypes.POINTER(u64), ctypes.POINTER(u64)],
     "dc_plan_destroy": [vp],
     "dc_plan_query": [vp, ctypes.POINTER(PlanInfo)],
     "dc_plan_objects": [vp, ctypes.POINTER(Object), u64, ctypes.POINTER(u64)],
@@ -109,6 +111,10 @@ _SIGS = {
     "dc_attach": [vp, vp],
     "dc_detach": [vp, vp],
     "dc_resolve_chain": [vp, u64, ctypes.POINTER(Step), u32, vp, ctypes.POINTER(Chain)],
+    "dc_chain_to_device": [vp, vp, u32, vp, ctypes.POINTER(Step), u32, vp, u64, vp, ctypes.POINTER(Chain)],
+    "dc_chain_run_kernel": [vp, ctypes.POINTER(Chain), u32, ctypes.c_double, ctypes.c_double, ctypes.c_float,
+                            ctypes.c_float, vp],
+    "dc_chain_copy_back": [vp, vp, u32, vp, ctypes.POINTER(Step), u32, ctypes.POINTER(Chain), vp],
     "dc_run_kernel": [vp, ctypes.POINTER(KernelArgs), vp],
     "dc_out_bytes": [vp, ctypes.POINTER(KernelArgs), ctypes.POINTER(u64)],
     "dc_copy_back": [vp, u32, vp],
@@ -237,11 +243,20 @@ class Schema:
 
 class Plan:
     def __init__(self, schema: Schema, root_type: int, roots: Sequence[int], align: int = 64,
-                 ctx: Optional[Context] = None):
+                 ctx: Optional[Context] = None, follow: Optional[Sequence[int]] = None):
+        """follow: None, or one bitmask per type over its field list (a
+        selective deep copy follows only the set fields)."""
         self._roots = (vp * max(1, len(roots)))(*roots)
         h, ab, sb = vp(), u64(), u64()
-        _check(load().dc_plan_create(ctx.h if ctx else None, schema.h, root_type, self._roots, len(roots), align,
-                                     ctypes.byref(h), ctypes.byref(ab), ctypes.byref(sb)), "dc_plan_create")
+        if follow is None:
+            _check(load().dc_plan_create(ctx.h if ctx else None, schema.h, root_type, self._roots, len(roots),
+                                         align, ctypes.byref(h), ctypes.byref(ab), ctypes.byref(sb)),
+                   "dc_plan_create")
+        else:
+            fm = (u32 * max(1, len(follow)))(*follow)
+            _check(load().dc_plan_create_selective(ctx.h if ctx else None, schema.h, root_type, self._roots,
+                                                   len(roots), align, fm, len(follow), ctypes.byref(h),
+                                                   ctypes.byref(ab), ctypes.byref(sb)), "dc_plan_create_selective")
         self.h = h
         self.schema = schema
         self.arena_bytes = ab.value
@@ -362,6 +377,38 @@ class Tree:
             self.release()
         except Exception:
             pass
+
+
+class ChainCopy:
+    """The pointerchain transfer scheme: only the array at the end of a chain
+    is copied to the device (into `buf`, a torch uint8 device tensor)."""
+
+    def __init__(self, ctx: Context, schema: Schema, root_type: int, root: int, chain, buf, stream=None):
+        self.ctx, self.schema, self.root_type, self.root, self.buf = ctx, schema, root_type, root, buf
+        self._steps = steps_array(chain)
+        self._n = len(chain)
+        self.c = Chain()
+        _check(load().dc_chain_to_device(ctx.h, schema.h, root_type, root, self._steps, self._n, _dev_ptr(buf),
+                                         buf.numel(), _stream_ptr(stream), ctypes.byref(self.c)),
+               "dc_chain_to_device")
+
+    @property
+    def count(self):
+        return self.c.count
+
+    @property
+    def kind(self):
+        return KIND_NAME[self.c.kind]
+
+    def run_kernel(self, iters=1, a=1.0, b=0.0, af=None, bf=None, stream=None):
+        af = float(np.float32(a)) if af is None else af
+        bf = float(np.float32(b)) if bf is None else bf
+        _check(load().dc_chain_run_kernel(self.ctx.h, ctypes.byref(self.c), iters, a, b, af, bf,
+                                          _stream_ptr(stream)), "dc_chain_run_kernel")
+
+    def copy_back(self, stream=None):
+        _check(load().dc_chain_copy_back(self.ctx.h, self.schema.h, self.root_type, self.root, self._steps,
+                                         self._n, ctypes.byref(self.c), _stream_ptr(stream)), "dc_chain_copy_back")
 
 
 def _tune(tune):

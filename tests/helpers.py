@@ -8,10 +8,10 @@ def dc_schema(types):
     return dc.Schema(types)
 
 
-def plan_of(t, align=64):
+def plan_of(t, align=64, follow=None):
     from paper_1906_01128_amd import dc
     schema = dc_schema(t.types)
-    return dc.Plan(schema, t.root_type, t.roots, align=align)
+    return dc.Plan(schema, t.root_type, t.roots, align=align, follow=follow)
 
 
 def same_objects(plan_objs, oracle_objs):

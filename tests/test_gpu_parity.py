@@ -36,16 +36,16 @@ def _alloc(n):
 class Copy:
     """A tree deep-copied by libdc, plus the oracle's copy at the same base."""
 
-    def __init__(self, ctx, t, align=64, relocate=True):
+    def __init__(self, ctx, t, align=64, relocate=True, follow=None):
         from paper_1906_01128_amd import dc
         self.t = t
         self.schema = dc.Schema(t.types)
-        self.plan = dc.Plan(self.schema, t.root_type, t.roots, align=align)
+        self.plan = dc.Plan(self.schema, t.root_type, t.roots, align=align, follow=follow)
         self.arena = _alloc(self.plan.arena_bytes)
         self.scratch = _alloc(self.plan.scratch_bytes)
         self.tree = dc.Tree(ctx, self.plan, self.arena, self.scratch, relocate=relocate)
         self.base = self.arena.data_ptr()
-        self.oracle = orc.OracleCopy(t.types, t.root_type, t.roots, align, self.base)
+        self.oracle = orc.OracleCopy(t.types, t.root_type, t.roots, align, self.base, follow=follow)
 
     def device_arena(self):
         torch.cuda.synchronize()

@@ -1,0 +1,119 @@
+"""GPU parity of the selective deep copy and of the pointerchain transfer
+scheme (Section 3: only the array a chain ends in travels), against the
+oracle, bit for bit."""
+import ctypes
+import random
+
+import numpy as np
+import pytest
+
+import fixtures as fx
+import oracle as orc
+from tests.test_gpu_parity import Copy, assert_same_bytes, ctx  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_selective_random(ctx, seed):
+    rng = random.Random(3000 + seed)
+    follow = [rng.getrandbits(3), rng.getrandbits(2)]
+    t = fx.random_tree(seed, max_objects=14, nroots=1 + seed % 3)
+    c = Copy(ctx, t, follow=follow)
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), f"selective {follow}")
+    c.tree.check()
+
+
+@pytest.mark.parametrize("follow", [[0b10], [0b01], [0b11]])
+def test_selective_linear_then_kernel(ctx, follow):
+    t = fx.linear(k=5, n=5000, scheme=0)
+    c = Copy(ctx, t, follow=follow)
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "selective linear copy")
+    c.tree.run_kernel(select="all", iters=2, a=1.0001, b=0.5)
+    c.oracle.run_kernel(1.0001, 0.5, iters=2, select="all")
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "selective linear after kernel")
+
+
+def test_selective_md_leaves_only_positions(ctx):
+    """MD simulations with only the position arrays of each cell followed."""
+    t = fx.md(seed=11, nsims=30, cells_lo=2, cells_hi=20, mean_atoms=6)
+    follow = [(1 << len(ty.fields)) - 1 for ty in t.types]
+    follow[-1] = 1  # the cell type keeps its first array only
+    c = Copy(ctx, t, follow=follow)
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "selective md")
+    c.tree.run_kernel(select="all", iters=1, a=0.75, b=2.0)
+    c.oracle.run_kernel(0.75, 2.0, iters=1, select="all")
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "selective md after kernel")
+
+
+# ---- the pointerchain transfer scheme ---------------------------------------------------
+
+
+def _chain_to_last(k):
+    return [(1, 0)] * (k - 1) + [(0, 0)]
+
+
+@pytest.mark.parametrize("k,n,iters", [(1, 1, 1), (4, 1000, 3), (8, 12345, 2), (2, 0, 1),
+                                            (8, (1 << 20) + 3, 5)])
+def test_pointerchain_linear(ctx, k, n, iters):
+    from paper_1906_01128_amd import dc
+    t = fx.linear(seed=fx.SEED_BASE + 41, k=k, n=n, scheme=1)
+    chain = _chain_to_last(k)
+    ref = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 0)
+    addr, count, kind = ref.resolve_chain(0, chain)
+    assert count == n and kind == "f64"
+    ref.run_kernel(1.0001, -0.5, iters=iters, select="leaf", chain=chain)
+    want = ref.arena()[addr:addr + 8 * n].view(np.float64).copy()
+
+    schema = dc.Schema(t.types)
+    buf = torch.zeros(max(8 * n, 16), dtype=torch.uint8, device="cuda")
+    cc = dc.ChainCopy(ctx, schema, t.root_type, t.roots[0], chain, buf)
+    assert cc.count == n and cc.kind == "f64"
+    torch.cuda.synchronize()
+    host_before = np.ctypeslib.as_array((ctypes.c_double * max(n, 1)).from_address(
+        ref.objects()[-1]["host"]))[:n].copy()
+    assert np.array_equal(buf[:8 * n].cpu().numpy().view(np.float64), host_before), "leaf transfer"
+    cc.run_kernel(iters=iters, a=1.0001, b=-0.5)
+    cc.copy_back()
+    host_after = np.ctypeslib.as_array((ctypes.c_double * max(n, 1)).from_address(
+        ref.objects()[-1]["host"]))[:n]
+    assert np.array_equal(host_after.view(np.uint64), want.view(np.uint64)), "pointerchain result"
+
+
+def test_pointerchain_fp32_wide(ctx):
+    from paper_1906_01128_amd import dc
+    t = fx.wide(seed=77, f1=4, f2=4, lo=1, hi=3001)
+    chain = [(0, 2), (0, 3), (0, 0)]   # root -> mid[2] -> leaf[3] -> its FP32 array
+    ref = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 0)
+    addr, count, kind = ref.resolve_chain(0, chain)
+    assert kind == "f32"
+    ref.run_kernel(0.999, 0.125, iters=4, select="leaf", chain=chain)
+    want = ref.arena()[addr:addr + 4 * count].view(np.uint32).copy()
+    host = next(int(o["host"]) for o in ref.objects() if int(o["off"]) == addr)
+    schema = dc.Schema(t.types)
+    buf = torch.zeros(4 * count + 64, dtype=torch.uint8, device="cuda")
+    cc = dc.ChainCopy(ctx, schema, t.root_type, t.roots[0], chain, buf)
+    cc.run_kernel(iters=4, a=0.999, b=0.125)
+    cc.copy_back()
+    got = np.ctypeslib.as_array((ctypes.c_uint32 * count).from_address(host))
+    assert np.array_equal(got, want)
+
+
+def test_pointerchain_errors(ctx):
+    from paper_1906_01128_amd import dc
+    t = fx.linear(seed=fx.SEED_BASE + 42, k=3, n=100, scheme=1)
+    schema = dc.Schema(t.types)
+    buf = torch.zeros(800, dtype=torch.uint8, device="cuda")
+    with pytest.raises(dc.DcError):     # level 0 has no data array: a null pointer
+        dc.ChainCopy(ctx, schema, 0, t.roots[0], [(0, 0)], buf)
+    with pytest.raises(dc.DcError):     # the chain ends in a struct array
+        dc.ChainCopy(ctx, schema, 0, t.roots[0], [(1, 0)], buf)
+    with pytest.raises(dc.DcError):     # index past the next-level array
+        dc.ChainCopy(ctx, schema, 0, t.roots[0], [(1, 1), (1, 0), (0, 0)], buf)
+    with pytest.raises(dc.DcError):     # buffer too small
+        dc.ChainCopy(ctx, schema, 0, t.roots[0], [(1, 0), (1, 0), (0, 0)], buf[:799])
+    with pytest.raises(dc.DcError):     # misaligned buffer
+        dc.ChainCopy(ctx, schema, 0, t.roots[0], [(1, 0), (1, 0), (0, 0)], buf[8:])
+    cc = dc.ChainCopy(ctx, schema, 0, t.roots[0], [(1, 0), (1, 0), (0, 0)], buf)
+    assert cc.count == 100
