@@ -229,6 +229,32 @@ dc_status dc_chain_run_kernel(dc_ctx ctx, const dc_chain* c, uint32_t iters, dou
 dc_status dc_chain_copy_back(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* root, const dc_step* steps,
                              uint32_t nsteps, const dc_chain* c, void* stream);
 
+/* Scalar chains (Section 3, scalar variables): a scalar member reached by a
+ * chain is copied into a temporary before a region and written back through
+ * the same chain when the region ends, so the structure sees the update. */
+typedef struct {
+  uint64_t root_index;
+  const dc_step* steps; /* each step: pointer field, then the element to move to */
+  uint32_t nsteps;      /* 0: a member of the root struct itself (at most 32) */
+  uint32_t offset;      /* byte offset of the scalar in the element reached last */
+  uint32_t bytes;       /* 1, 4 or 8; may not overlap a pointer member */
+  uint32_t reserved;
+} dc_scalar_ref;
+/* Walks every chain on the device (attached tree) and stores each scalar,
+ * zero-extended, in d_temps[i] (device, 8 bytes per ref, 8-byte aligned).
+ * Returns when the values are in d_temps.
+ * Errors: DC_E_INVAL (bad field, a step through a primitive array, bytes,
+ * overlap with a pointer member), DC_E_RANGE (null pointer or index past an
+ * array on the way), DC_E_STATE (not attached; the device walk disagreed
+ * with the plan). */
+dc_status dc_scalar_declare(dc_tree tree, const dc_scalar_ref* refs, uint32_t nrefs, void* d_temps, void* stream);
+/* Writes the low `bytes` bytes of d_temps[i] back to the scalar its chain
+ * reaches, walking the chain again on the device. Returns when written.
+ * Errors as dc_scalar_declare. dc_copy_back with DC_COPY_SCALARS then takes
+ * the values to the host structure. */
+dc_status dc_scalar_update(dc_tree tree, const dc_scalar_ref* refs, uint32_t nrefs, const void* d_temps,
+                           void* stream);
+
 /* ---- leaf kernels (Algorithm 2 step 4) --------------------------------------------- */
 
 enum { DC_MODE_RESOLVED = 0, DC_MODE_DEREF_EACH = 1 };

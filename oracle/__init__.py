@@ -78,6 +78,9 @@ def _load():
         lib.or_resolve_chain.argtypes = [vp, u64, ctypes.POINTER(u32), ctypes.POINTER(u64), u32,
                                          ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32)]
         lib.or_resolve_chain.restype = ctypes.c_int
+        lib.or_scalar_chain.argtypes = [vp, u64, ctypes.POINTER(u32), ctypes.POINTER(u64), u32, u32, u32,
+                                        ctypes.POINTER(u64)]
+        lib.or_scalar_chain.restype = ctypes.c_int
         lib.or_run_kernel.argtypes = [vp, ctypes.c_int, u64, ctypes.POINTER(u32), ctypes.POINTER(u64), u32, u32,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.c_float, vp, u64]
         lib.or_run_kernel.restype = ctypes.c_int
@@ -180,6 +183,16 @@ class OracleCopy:
         if rc:
             raise OracleError(rc, "or_resolve_chain")
         return addr.value, count.value, OR_KIND_NAME[kind.value]
+
+    def scalar_chain(self, root_index, chain, offset, nbytes) -> int:
+        """Buffer address (as laid out at `base`) of a scalar member reached
+        by `chain` (struct steps only; empty for the root's own member)."""
+        fields, index, n = _chain_arrays(chain)
+        addr = ctypes.c_uint64()
+        rc = _load().or_scalar_chain(self._h, root_index, fields, index, n, offset, nbytes, ctypes.byref(addr))
+        if rc:
+            raise OracleError(rc, "or_scalar_chain")
+        return addr.value
 
     def out_bytes(self, select="all", root_index=0, chain=None) -> int:
         fields, index, n = _chain_arrays(chain)

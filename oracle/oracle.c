@@ -394,6 +394,40 @@ int or_resolve_chain(const or_copy* c, uint64_t root_index, const uint32_t* fiel
   return OR_E_INVAL;
 }
 
+/* A scalar member reached through a chain (Section 3, scalar variables):
+ * every step reads a pointer member and moves to element index[s] of the
+ * struct array it points to; the scalar is `bytes` bytes at `offset` of the
+ * element the last step lands on (of the root itself when nsteps is 0). */
+int or_scalar_chain(const or_copy* c, uint64_t root_index, const uint32_t* fields, const uint64_t* index,
+                    uint32_t nsteps, uint32_t offset, uint32_t bytes, uint64_t* addr) {
+  if (root_index >= c->nroots) return OR_E_INVAL;
+  if (bytes != 1 && bytes != 4 && bytes != 8) return OR_E_INVAL;
+  const or_object* cur = &c->objs[c->root_obj[root_index]];
+  uint64_t elem = 0;
+  for (uint32_t s = 0; s < nsteps; s++) {
+    const or_type* t = &c->types[cur->type];
+    if (fields[s] >= t->nfields) return OR_E_INVAL;
+    const or_field* f = &t->fields[fields[s]];
+    if (f->kind != OR_STRUCT) return OR_E_INVAL;
+    const uint8_t* e = c->arena + cur->off + elem * t->size;
+    uint64_t p;
+    memcpy(&p, e + f->offset, 8);
+    if (p == 0) return OR_E_RANGE;
+    uint64_t n;
+    int rc = field_count(f, e, &n);
+    if (rc) return rc;
+    if (index[s] >= n) return OR_E_RANGE;
+    int64_t j = object_at(c, p - c->base);
+    if (j < 0) return OR_E_RANGE;
+    cur = &c->objs[j];
+    elem = index[s];
+  }
+  const or_type* t = &c->types[cur->type];
+  if ((uint64_t)offset + bytes > t->size) return OR_E_RANGE;
+  *addr = c->base + cur->off + elem * t->size + offset;
+  return OR_OK;
+}
+
 double or_fma64(double x, double a, double b) { return fma(x, a, b); }
 float or_fma32(float x, float a, float b) { return fmaf(x, a, b); }
 

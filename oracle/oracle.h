@@ -89,6 +89,15 @@ uint64_t or_payload_bytes(const or_copy* c); /* sum of object bytes */
 int or_resolve_chain(const or_copy* c, uint64_t root_index, const uint32_t* fields, const uint64_t* index,
                      uint32_t nsteps, uint64_t* addr, uint64_t* count, uint32_t* kind);
 
+/* The buffer address (as laid out at `base`) of a scalar member reached by a
+ * chain: each step reads pointer field fields[s] and moves to element
+ * index[s] of the struct array it points to; the scalar is `bytes` (1, 4 or
+ * 8) bytes at `offset` in the element reached last (the root if nsteps == 0).
+ * Reading it there and writing a new value back there are the two halves of
+ * a scalar chain's declare and update (Section 3). */
+int or_scalar_chain(const or_copy* c, uint64_t root_index, const uint32_t* fields, const uint64_t* index,
+                    uint32_t nsteps, uint32_t offset, uint32_t bytes, uint64_t* addr);
+
 /* select 0: the leaf at the end of the chain; 1: every FP32/FP64 array.
  * out == NULL: in place in the buffer. Otherwise the results go to `out`,
  * leaves in layout order, each at the next multiple of the layout alignment

@@ -232,6 +232,7 @@ dc_status dc_ctx_destroy(dc_ctx c) {
   }
   if (c->small) (void)hipHostFree(c->small);
   if (c->dev_hdr) (void)hipFree(c->dev_hdr);
+  if (c->aux) (void)hipFree(c->aux);
   delete c->pool;
   delete c;
   return DC_OK;

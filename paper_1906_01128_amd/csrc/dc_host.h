@@ -83,6 +83,8 @@ struct dc_ctx_s {
   int next = 0;
   uint8_t* small = nullptr;  // pinned scratch for header reads
   dc::DevHeader* dev_hdr = nullptr;  // device header for kernels outside a tree
+  uint8_t* aux = nullptr;            // device buffer for per-call descriptors (grows)
+  uint64_t aux_bytes = 0;
   dc::Pool* pool = nullptr;
 };
 

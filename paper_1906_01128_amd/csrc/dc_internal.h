@@ -159,6 +159,19 @@ struct HopArgs {
   uint64_t hop_off[kMaxChainSteps];
 };
 
+// A scalar member reached through a chain of struct steps.
+struct DevScalar {
+  uint64_t root_off;    // arena offset of the root struct
+  uint64_t expect_off;  // arena offset of the scalar according to the plan
+  uint32_t hop_lo, nhops;
+  uint32_t offset, bytes;
+};
+struct DevScalarHop {
+  uint32_t field_off;  // pointer member in the current element
+  uint32_t elem_size;  // element size of the struct array it points to
+  uint64_t index;      // element to move to
+};
+
 // ---- launchers (dc_kernels.hip) ------------------------------------------------
 struct Tables {  // device addresses of the scratch tables
   DevHeader* hdr;
@@ -182,6 +195,9 @@ struct Tables {  // device addresses of the scratch tables
 };
 
 hipError_t launch_relocate(const Tables& t, bool attach, hipStream_t s);
+// update 0: temps[i] = the scalar (zero-extended); 1: the scalar = low bytes of temps[i]
+hipError_t launch_scalar(const Tables& t, const DevScalar* refs, const DevScalarHop* hops, uint32_t n,
+                         uint64_t* temps, int update, hipStream_t s);
 hipError_t launch_resolve_chain(const Tables& t, const ChainArgs& c, hipStream_t s);
 hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint64_t ntiles, bool deref_each, hipStream_t s);
 // one FP32/FP64 array at device address `base`, resolved once before the

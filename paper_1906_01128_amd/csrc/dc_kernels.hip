@@ -220,6 +220,42 @@ __global__ void k_resolve_chain(Tables t, ChainArgs c) {
   h->chain_status = kErrNullChain;
 }
 
+// One thread per scalar chain: walk the chain through the relocated arena,
+// check that it lands where the plan says, then read or write the scalar.
+__global__ void __launch_bounds__(256) k_scalar(Tables t, const DevScalar* refs, const DevScalarHop* hops, uint32_t n,
+                                                uint64_t* temps, int update) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const DevScalar r = refs[i];
+  uint64_t elem = (uint64_t)t.arena + r.root_off;
+  bool ok = true;
+  for (uint32_t k = 0; k < r.nhops && ok; k++) {
+    const DevScalarHop h = hops[r.hop_lo + k];
+    if (!in_arena(t, elem + h.field_off, 8)) {
+      ok = false;
+      break;
+    }
+    const uint64_t p = *(const uint64_t*)(elem + h.field_off);
+    ok = p != 0 && in_arena(t, p, (h.index + 1) * h.elem_size);
+    elem = p + h.index * h.elem_size;
+  }
+  const uint64_t addr = elem + r.offset;
+  if (!ok || addr != (uint64_t)t.arena + r.expect_off) {
+    atomicAdd(&t.hdr->err_count, 1u);
+    atomicCAS(&t.hdr->err_code, 0u, (uint32_t)kErrChain);
+    return;
+  }
+  uint8_t* sp = (uint8_t*)addr;
+  uint8_t* tp = (uint8_t*)&temps[i];
+  if (update) {
+    for (uint32_t b = 0; b < r.bytes; b++) sp[b] = tp[b];
+  } else {
+    uint64_t v = 0;
+    for (uint32_t b = 0; b < r.bytes; b++) v |= (uint64_t)sp[b] << (8 * b);
+    temps[i] = v;
+  }
+}
+
 // ---- leaf arithmetic ------------------------------------------------------------------
 
 union Vec16 {
@@ -614,6 +650,13 @@ hipError_t launch_relocate(const Tables& t, bool attach, hipStream_t s) {
   if (t.nseg == 0) return hipSuccess;
   const uint64_t grid = t.nseg < 65536 ? t.nseg : 65536;
   hipLaunchKernelGGL(k_relocate, dim3((uint32_t)grid), dim3(kRelocBlock), 0, s, t, attach ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalar(const Tables& t, const DevScalar* refs, const DevScalarHop* hops, uint32_t n,
+                         uint64_t* temps, int update, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scalar, dim3((n + 255) / 256), dim3(256), 0, s, t, refs, hops, n, temps, update);
   return hipGetLastError();
 }
 

@@ -49,6 +49,11 @@ class Chain(ctypes.Structure):
     _fields_ = [("dev_addr", u64), ("count", u64), ("kind", u32), ("reserved", u32)]
 
 
+class ScalarRef(ctypes.Structure):
+    _fields_ = [("root_index", ctypes.c_uint64), ("steps", ctypes.c_void_p), ("nsteps", ctypes.c_uint32),
+                ("offset", ctypes.c_uint32), ("bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 class Object(ctypes.Structure):
     _fields_ = [("host_addr", u64), ("offset", u64), ("bytes", u64), ("count", u64), ("kind", u32), ("type_id", u32)]
 
@@ -115,6 +120,8 @@ _SIGS = {
     "dc_chain_run_kernel": [vp, ctypes.POINTER(Chain), u32, ctypes.c_double, ctypes.c_double, ctypes.c_float,
                             ctypes.c_float, vp],
     "dc_chain_copy_back": [vp, vp, u32, vp, ctypes.POINTER(Step), u32, ctypes.POINTER(Chain), vp],
+    "dc_scalar_declare": [vp, ctypes.POINTER(ScalarRef), u32, vp, vp],
+    "dc_scalar_update": [vp, ctypes.POINTER(ScalarRef), u32, vp, vp],
     "dc_run_kernel": [vp, ctypes.POINTER(KernelArgs), vp],
     "dc_out_bytes": [vp, ctypes.POINTER(KernelArgs), ctypes.POINTER(u64)],
     "dc_copy_back": [vp, u32, vp],
@@ -350,6 +357,31 @@ class Tree:
 
     def check(self, stream=None):
         _check(load().dc_tree_check(self.h, _stream_ptr(stream)), "dc_tree_check")
+
+    @staticmethod
+    def _scalar_refs(refs):
+        """refs: (root_index, chain, offset, nbytes) tuples; chain as for
+        resolve_chain, each step landing on an element."""
+        arr = (ScalarRef * max(1, len(refs)))()
+        keep = []
+        for i, (root, chain, off, nb) in enumerate(refs):
+            st = steps_array(chain)
+            keep.append(st)
+            arr[i].root_index, arr[i].steps = root, ctypes.cast(st, ctypes.c_void_p)
+            arr[i].nsteps, arr[i].offset, arr[i].bytes = len(chain), off, nb
+        return arr, keep
+
+    def scalar_declare(self, refs, temps, stream=None):
+        """Copies each scalar into temps (a device tensor of 8 bytes per ref)."""
+        arr, _keep = self._scalar_refs(refs)
+        _check(load().dc_scalar_declare(self.h, arr, len(refs), _dev_ptr(temps), _stream_ptr(stream)),
+               "dc_scalar_declare")
+
+    def scalar_update(self, refs, temps, stream=None):
+        """Writes temps back through each chain."""
+        arr, _keep = self._scalar_refs(refs)
+        _check(load().dc_scalar_update(self.h, arr, len(refs), _dev_ptr(temps), _stream_ptr(stream)),
+               "dc_scalar_update")
 
     def batch_run(self, a=1.0001, b=0.5, tune=None, attach=True, detach=False, out=None, stream=None):
         ka = _kargs(mode="resolved", select="all", iters=1, a=a, b=b, out=out)
