@@ -255,6 +255,28 @@ dc_status dc_scalar_declare(dc_tree tree, const dc_scalar_ref* refs, uint32_t nr
 dc_status dc_scalar_update(dc_tree tree, const dc_scalar_ref* refs, uint32_t nrefs, const void* d_temps,
                            void* stream);
 
+/* Molecular-dynamics leaf kernel on sibling leaves (the atoms-in-cells
+ * structure of the pointerchain example in Section 3): for every element of
+ * struct type `type`, `steps` times, over the FP64 arrays its members x_field,
+ * v_field and f_field point to (positions, velocities, forces):
+ *   v <- fma(f, dt_over_m, v)   then   x <- fma(v, dt, x)
+ * one rounding per fma. Each element's three arrays must have equal counts
+ * and be all null (skipped) or all non-null; no array may serve two elements
+ * or two roles. The element list is built on the first call for a
+ * (type, fields) choice and kept in device memory the library owns until
+ * dc_tree_release. Asynchronous on `stream`.
+ * Errors: DC_E_INVAL (type, fields, counts, a partly null element),
+ * DC_E_CONFLICT (a shared array), DC_E_STATE (not attached). */
+typedef struct {
+  uint32_t type;
+  uint32_t x_field, v_field, f_field;
+  uint32_t steps;
+  uint32_t reserved;
+  double dt;
+  double dt_over_m;
+} dc_kick_drift_args;
+dc_status dc_run_kick_drift(dc_tree tree, const dc_kick_drift_args* args, void* stream);
+
 /* ---- leaf kernels (Algorithm 2 step 4) --------------------------------------------- */
 
 enum { DC_MODE_RESOLVED = 0, DC_MODE_DEREF_EACH = 1 };
@@ -275,7 +297,11 @@ enum { DC_SELECT_CHAIN = 0, DC_SELECT_ALL_LEAVES = 1 };
  * receives the results as a leaf image: the selected leaves in arena order,
  * each at the next multiple of the plan alignment after the previous one's
  * end, the first at 0; the arena is left unchanged.
- * Asynchronous on `stream`. */
+ * Asynchronous on `stream`. No other work may write the arena's pointer
+ * members while a kernel runs on it: the per-access walks rely on the slots
+ * one checked walk per wavefront has validated.
+ * Errors reported by the kernel (a slot or leaf outside the arena) surface in
+ * dc_tree_check. */
 typedef struct {
   uint32_t mode;
   uint32_t select;

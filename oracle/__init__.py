@@ -6,8 +6,10 @@ cpu_baseline leg may import this package. It shares no code with the HIP path
 
 The C source (oracle.c) says what each step computes and which part of the
 paper it follows. Parity status: the walk/layout/copy/relocation, chain
-resolution, kernel and copy back are all pinned by tests under tests/
-(test_oracle_pins.py); nothing here is "parity unpinned".
+resolution, kernel and copy back are pinned by tests/test_oracle_pins.py, the
+selective walk by tests/test_selective.py, scalar chains by
+tests/test_scalar_chain.py and the kick-drift update by
+tests/test_kick_drift.py; nothing here is "parity unpinned".
 """
 from __future__ import annotations
 
@@ -81,6 +83,8 @@ def _load():
         lib.or_scalar_chain.argtypes = [vp, u64, ctypes.POINTER(u32), ctypes.POINTER(u64), u32, u32, u32,
                                         ctypes.POINTER(u64)]
         lib.or_scalar_chain.restype = ctypes.c_int
+        lib.or_kick_drift.argtypes = [vp, u32, u32, u32, u32, u32, ctypes.c_double, ctypes.c_double]
+        lib.or_kick_drift.restype = ctypes.c_int
         lib.or_run_kernel.argtypes = [vp, ctypes.c_int, u64, ctypes.POINTER(u32), ctypes.POINTER(u64), u32, u32,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.c_float, vp, u64]
         lib.or_run_kernel.restype = ctypes.c_int
@@ -209,6 +213,13 @@ class OracleCopy:
                                    a, b, af, bf, optr, olen)
         if rc:
             raise OracleError(rc, "or_run_kernel")
+
+    def kick_drift(self, type_id, x_field, v_field, f_field, dt, dt_over_m, steps=1):
+        """v <- fma(f, dt_over_m, v); x <- fma(v, dt, x) per time step on every
+        element of struct type `type_id`."""
+        rc = _load().or_kick_drift(self._h, type_id, x_field, v_field, f_field, steps, dt, dt_over_m)
+        if rc:
+            raise OracleError(rc, "or_kick_drift")
 
     def copy_back(self, scalars=False):
         rc = _load().or_copy_back(self._h, 1 if scalars else 0)

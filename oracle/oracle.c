@@ -512,6 +512,94 @@ int or_run_kernel(or_copy* c, int select, uint64_t root_index, const uint32_t* f
   return OR_OK;
 }
 
+/* The molecular-dynamics update of every element of struct type `type`
+ * (the paper's Listing of atoms in cells; a velocity-Verlet style kick then
+ * drift per time step, forces held fixed): for each of the element's count
+ * entries,
+ *   v <- fma(f, dt_over_m, v)     (kick)
+ *   x <- fma(v, dt, x)            (drift, with the kicked v)
+ * in binary64 with one rounding per fma. x, v and f are the arrays that pointer
+ * fields xf, vf and ff of the element point to; they must have equal counts,
+ * be all null or all non-null, and no array may belong to two elements or two
+ * roles. */
+int or_kick_drift(or_copy* c, uint32_t type, uint32_t xf, uint32_t vf, uint32_t ff, uint32_t steps, double dt,
+                  double dt_over_m) {
+  if (type >= c->ntypes) return OR_E_INVAL;
+  const or_type* t = &c->types[type];
+  if (xf >= t->nfields || vf >= t->nfields || ff >= t->nfields) return OR_E_INVAL;
+  if (xf == vf || xf == ff || vf == ff) return OR_E_INVAL;
+  const uint32_t fl[3] = {xf, vf, ff};
+  for (int r = 0; r < 3; r++)
+    if (t->fields[fl[r]].kind != OR_F64) return OR_E_INVAL;
+  uint8_t* used = calloc(c->nobjs ? c->nobjs : 1, 1);
+  if (!used) return OR_E_NOMEM;
+  int rc = OR_OK;
+  /* validation pass: every element's three arrays */
+  for (uint64_t i = 0; i < c->nobjs && rc == OR_OK; i++) {
+    const or_object* o = &c->objs[i];
+    if (o->kind != OR_STRUCT || o->type != type) continue;
+    for (uint64_t e = 0; e < o->count && rc == OR_OK; e++) {
+      const uint8_t* el = c->arena + o->off + e * t->size;
+      uint64_t p[3], n[3];
+      int nnull = 0;
+      for (int r = 0; r < 3 && rc == OR_OK; r++) {
+        memcpy(&p[r], el + t->fields[fl[r]].offset, 8);
+        rc = field_count(&t->fields[fl[r]], el, &n[r]);
+        nnull += p[r] == 0;
+      }
+      if (rc) break;
+      if (nnull == 3) continue;
+      if (nnull != 0 || n[0] != n[1] || n[0] != n[2]) {
+        rc = OR_E_INVAL;
+        break;
+      }
+      for (int r = 0; r < 3; r++) {
+        int64_t j = object_at(c, p[r] - c->base);
+        if (j < 0) {
+          rc = OR_E_RANGE;
+          break;
+        }
+        if (used[j]) {
+          rc = OR_E_CONFLICT;
+          break;
+        }
+        used[j] = 1;
+      }
+    }
+  }
+  free(used);
+  if (rc) return rc;
+  for (uint32_t s = 0; s < steps; s++) {
+    for (uint64_t i = 0; i < c->nobjs; i++) {
+      const or_object* o = &c->objs[i];
+      if (o->kind != OR_STRUCT || o->type != type) continue;
+      for (uint64_t e = 0; e < o->count; e++) {
+        const uint8_t* el = c->arena + o->off + e * t->size;
+        uint64_t px, pv, pf, n = 0;
+        memcpy(&px, el + t->fields[xf].offset, 8);
+        memcpy(&pv, el + t->fields[vf].offset, 8);
+        memcpy(&pf, el + t->fields[ff].offset, 8);
+        if (px == 0) continue;
+        field_count(&t->fields[xf], el, &n);
+        uint8_t* X = c->arena + (px - c->base);
+        uint8_t* V = c->arena + (pv - c->base);
+        const uint8_t* F = c->arena + (pf - c->base);
+        for (uint64_t k = 0; k < n; k++) {
+          double x, v, f;
+          memcpy(&x, X + 8 * k, 8);
+          memcpy(&v, V + 8 * k, 8);
+          memcpy(&f, F + 8 * k, 8);
+          v = fma(f, dt_over_m, v);
+          x = fma(v, dt, x);
+          memcpy(V + 8 * k, &v, 8);
+          memcpy(X + 8 * k, &x, 8);
+        }
+      }
+    }
+  }
+  return OR_OK;
+}
+
 int or_copy_back(const or_copy* c, int scalars) {
   for (uint64_t i = 0; i < c->nobjs; i++) {
     const or_object* o = &c->objs[i];

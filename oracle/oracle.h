@@ -109,6 +109,15 @@ int or_run_kernel(or_copy* c, int select, uint64_t root_index, const uint32_t* f
 uint64_t or_out_bytes(const or_copy* c, int select, uint64_t root_index, const uint32_t* fields,
                       const uint64_t* index, uint32_t nsteps);
 
+/* Molecular-dynamics kick then drift, `steps` times, on every element of
+ * struct type `type` (in place in the buffer): v <- fma(f, dt_over_m, v),
+ * then x <- fma(v, dt, x), over the FP64 arrays that pointer fields xf, vf
+ * and ff point to. OR_E_INVAL for unequal counts, a partly null triple or a
+ * field that is not FP64; OR_E_CONFLICT when an array serves two elements
+ * or roles. */
+int or_kick_drift(or_copy* c, uint32_t type, uint32_t xf, uint32_t vf, uint32_t ff, uint32_t steps, double dt,
+                  double dt_over_m);
+
 /* Writes primitive arrays back to their host addresses; scalars != 0 also
  * writes the non-pointer bytes of struct elements. */
 int or_copy_back(const or_copy* c, int scalars);

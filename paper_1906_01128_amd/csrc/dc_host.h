@@ -185,6 +185,10 @@ struct dc_plan_s {
   uint64_t arena_bytes = 0, payload_bytes = 0, leaf_bytes = 0, nslots_nonnull = 0;
 };
 
+namespace dc {
+struct KdTables;
+}
+
 struct dc_tree_s {
   dc_ctx ctx = nullptr;
   dc_plan plan = nullptr;
@@ -197,6 +201,7 @@ struct dc_tree_s {
   uint32_t tile_T = 0;              // tile size of the tile list in scratch
   uint64_t ntiles = 0;
   hipEvent_t tiles_ev = nullptr;    // recorded after the tile index was built
+  dc::KdTables* kd = nullptr;       // element list of the kick-drift kernel (device)
 };
 
 namespace dc {
@@ -207,6 +212,8 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
 // made on another stream).
 dc_status tree_ensure_tiles(dc_tree t, uint32_t T, hipStream_t s);
 dc_status tree_check(dc_tree t, hipStream_t s);
+// Frees the kick-drift tables of a tree.
+void kd_free(dc_tree t);
 // The tile list dc_run_kernel uses for every-leaf kernels.
 dc_status tree_prepare_leaf_tiles(dc_tree t, hipStream_t s);
 // Compute tiles of at most T chunks and kTileMaxLeaves leaves, in order.

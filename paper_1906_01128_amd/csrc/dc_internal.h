@@ -172,6 +172,21 @@ struct DevScalarHop {
   uint64_t index;      // element to move to
 };
 
+// One element of the molecular-dynamics update: where its x, v and f slots
+// are and how many doubles each array holds.
+struct DevTriple {
+  uint64_t elem_off;  // arena offset of the struct element
+  uint64_t count;     // doubles per array
+};
+struct KickDriftArgs {
+  const DevTriple* tri;
+  const uint64_t* pre;  // ntri + 1 entries: prefix of 16-byte chunks
+  const DevTile* tiles;
+  uint64_t ntiles;
+  uint32_t x_off, v_off, f_off, pad;
+  double dt, dt_over_m;
+};
+
 // ---- launchers (dc_kernels.hip) ------------------------------------------------
 struct Tables {  // device addresses of the scratch tables
   DevHeader* hdr;
@@ -198,6 +213,7 @@ hipError_t launch_relocate(const Tables& t, bool attach, hipStream_t s);
 // update 0: temps[i] = the scalar (zero-extended); 1: the scalar = low bytes of temps[i]
 hipError_t launch_scalar(const Tables& t, const DevScalar* refs, const DevScalarHop* hops, uint32_t n,
                          uint64_t* temps, int update, hipStream_t s);
+hipError_t launch_kick_drift(const Tables& t, const KickDriftArgs& k, hipStream_t s);
 hipError_t launch_resolve_chain(const Tables& t, const ChainArgs& c, hipStream_t s);
 hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint64_t ntiles, bool deref_each, hipStream_t s);
 // one FP32/FP64 array at device address `base`, resolved once before the

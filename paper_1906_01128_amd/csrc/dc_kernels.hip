@@ -358,8 +358,14 @@ __device__ __forceinline__ uint64_t walk_load(uint64_t addr) {
 // walk each; a wavefront's 64 lanes access 64 consecutive elements per walk.
 // The U walks of a wavefront advance hop by hop together, so their scalar
 // loads overlap; the hop offsets (at most MAXH) are held in scalar registers.
-// A slot or leaf outside the arena is replaced by the arena base before it is
-// read, and the wavefront then stops after reporting it.
+//
+// Bounds: a wavefront first walks the chain once with every slot checked
+// against the arena (a slot outside it is replaced by the arena base before
+// it is read; the wavefront then reports and stops). The U per-access walks
+// that follow read the same slots, which no kernel of this library writes
+// while the walk runs, and must land on the checked address. Checking every
+// hop of every walk instead puts a vector compare on the scalar load chain
+// and costs about a fifth of the bandwidth.
 template <int U, int MAXH, typename T>
 __global__ void __launch_bounds__(256) k_stream_deref(Tables t, HopArgs h, uint64_t count, LeafArgs la) {
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
@@ -369,26 +375,34 @@ __global__ void __launch_bounds__(256) k_stream_deref(Tables t, HopArgs h, uint6
   uint64_t off[MAXH];
 #pragma unroll
   for (int j = 0; j < MAXH; j++) off[j] = j < (int)h.nhops ? h.hop_off[j] : 0;
-  uint64_t p[U];
   bool ok = size >= 8;
-#pragma unroll
-  for (int k = 0; k < U; k++) p[k] = B + h.root_off;
+  uint64_t q = B + h.root_off;
 #pragma unroll
   for (int j = 0; j < MAXH; j++) {
     if (j < (int)h.nhops) {
-#pragma unroll
-      for (int k = 0; k < U; k++) {
-        uint64_t slot = p[k] + off[j];
-        const bool in = slot - B <= size - 8;
-        ok = ok && in;
-        slot = in ? slot : B;
-        p[k] = walk_load(slot);
-      }
+      uint64_t slot = q + off[j];
+      const bool in = slot - B <= size - 8;
+      ok = ok && in;
+      slot = in ? slot : B;
+      q = walk_load(slot);
     }
   }
   const uint64_t need = count * sizeof(T);
+  ok = ok && q - B <= size && need <= size - (q - B);
+  if (!ok) {
+    if (lane == 0) report_wild(t.hdr);
+    return;
+  }
+  uint64_t p[U];
 #pragma unroll
-  for (int k = 0; k < U; k++) ok = ok && p[k] - B <= size && need <= size - (p[k] - B);
+  for (int k = 0; k < U; k++) p[k] = B + h.root_off;
+#pragma unroll
+  for (int j = 0; j < MAXH; j++)
+    if (j < (int)h.nhops)
+#pragma unroll
+      for (int k = 0; k < U; k++) p[k] = walk_load(p[k] + off[j]);
+#pragma unroll
+  for (int k = 0; k < U; k++) ok = ok && p[k] == q;
   if (!ok) {
     if (lane == 0) report_wild(t.hdr);
     return;
@@ -537,6 +551,92 @@ __global__ void __launch_bounds__(256) k_leaf_tiles(Tables t, LeafArgs la, uint6
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) leaf_tile<U, DEREF>(t, la, tile, lds);
 }
 
+// ---- molecular dynamics: kick then drift on sibling leaves ------------------------------
+//
+// One tile: a range of 16-byte chunks of the elements' arrays laid end to
+// end (each element contributes ceil(count / 2) chunks), at most
+// kTileMaxLeaves elements. The element's three array addresses are read once
+// per tile from its relocated slots (the resolved form of Section 3) and
+// checked against the arena; per chunk: v = fma(f, dt/m, v), x = fma(v, dt, x).
+constexpr size_t kKdLds = (size_t)(kTileMaxLeaves + 2) * 5 * 8;
+
+template <int U>
+__global__ void __launch_bounds__(256) k_kick_drift(Tables t, KickDriftArgs k) {
+  __shared__ __align__(16) uint8_t lds[kKdLds];
+  constexpr uint32_t N = kTileMaxLeaves + 2;
+  uint64_t* pre = (uint64_t*)lds;
+  uint64_t* xa = pre + N;
+  uint64_t* va = xa + N;
+  uint64_t* fa = va + N;
+  uint64_t* cnt = fa + N;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  for (uint64_t tile = blockIdx.x; tile < k.ntiles; tile += gridDim.x) {
+    const DevTile tl = k.tiles[tile];
+    const uint32_t e0 = tl.l_lo, nl = tl.l_hi - tl.l_lo + 1;
+    for (uint32_t i = tid; i < nl; i += bs) {
+      const DevTriple tr = k.tri[e0 + i];
+      const uint64_t el = (uint64_t)t.arena + tr.elem_off;
+      const uint64_t need = tr.count * 8;
+      uint64_t x = *(const g_u64*)(el + k.x_off), v = *(const g_u64*)(el + k.v_off),
+               f = *(const g_u64*)(el + k.f_off);
+      if (!in_arena(t, x, need) || !in_arena(t, v, need) || !in_arena(t, f, need)) {
+        report_wild(t.hdr);
+        x = v = f = 0;
+      }
+      pre[i] = k.pre[e0 + i];
+      xa[i] = x;
+      va[i] = v;
+      fa[i] = f;
+      cnt[i] = tr.count;
+    }
+    if (tid == 0) pre[nl] = k.pre[tl.l_hi + 1];
+    __syncthreads();
+    for (uint64_t c_lo = tl.c_lo; c_lo < tl.c_hi; c_lo += (uint64_t)bs * U) {
+      Vec16 X[U], V[U], F[U];
+      uint64_t xd[U], vd[U];
+      uint32_t ne[U];  // doubles in this chunk: 0, 1 or 2
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const uint64_t c = c_lo + (uint64_t)u * bs + tid;
+        ne[u] = 0;
+        xd[u] = vd[u] = 0;
+        if (c < tl.c_hi) {
+          const uint32_t i = find_leaf(pre, nl, c);
+          const uint64_t e = (c - pre[i]) * 2;  // first double of the chunk
+          ne[u] = xa[i] == 0 ? 0 : (cnt[i] - e >= 2 ? 2u : (uint32_t)(cnt[i] - e));
+          xd[u] = xa[i] + e * 8;
+          vd[u] = va[i] + e * 8;
+          if (ne[u] == 2) {
+            X[u].u = gload16(xd[u]);
+            V[u].u = gload16(vd[u]);
+            F[u].u = gload16(fa[i] + e * 8);
+          } else if (ne[u] == 1) {
+            X[u].d[0] = *(const g_double*)xd[u];
+            V[u].d[0] = *(const g_double*)vd[u];
+            F[u].d[0] = *(const g_double*)(fa[i] + e * 8);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        if (ne[u] == 2) {
+          V[u].d[0] = __builtin_fma(F[u].d[0], k.dt_over_m, V[u].d[0]);
+          V[u].d[1] = __builtin_fma(F[u].d[1], k.dt_over_m, V[u].d[1]);
+          X[u].d[0] = __builtin_fma(V[u].d[0], k.dt, X[u].d[0]);
+          X[u].d[1] = __builtin_fma(V[u].d[1], k.dt, X[u].d[1]);
+          gstore16(vd[u], V[u].u);
+          gstore16(xd[u], X[u].u);
+        } else if (ne[u] == 1) {
+          const double v1 = __builtin_fma(F[u].d[0], k.dt_over_m, V[u].d[0]);
+          *(g_double*)vd[u] = v1;
+          *(g_double*)xd[u] = __builtin_fma(v1, k.dt, X[u].d[0]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---- persistent relocate + compute ------------------------------------------------------------
 //
 // One launch, one device work queue. Items: [attach units][compute tile
@@ -657,6 +757,13 @@ hipError_t launch_scalar(const Tables& t, const DevScalar* refs, const DevScalar
                          uint64_t* temps, int update, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_scalar, dim3((n + 255) / 256), dim3(256), 0, s, t, refs, hops, n, temps, update);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(const Tables& t, const KickDriftArgs& k, hipStream_t s) {
+  if (k.ntiles == 0) return hipSuccess;
+  const uint64_t grid = k.ntiles < (1u << 20) ? k.ntiles : (1u << 20);
+  hipLaunchKernelGGL(k_kick_drift<4>, dim3((uint32_t)grid), dim3(256), 0, s, t, k);
   return hipGetLastError();
 }
 

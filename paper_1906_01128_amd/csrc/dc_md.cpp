@@ -1,0 +1,168 @@
+// libdc molecular-dynamics leaf kernel: kick then drift over the sibling
+// position, velocity and force arrays of every element of one struct type
+// (the atoms-in-cells structure of the paper's pointerchain example).
+#include <string.h>
+
+#include <algorithm>
+#include <unordered_set>
+
+#include "dc_host.h"
+
+namespace dc {
+
+struct KdTables {
+  uint32_t type = ~0u, xf = 0, vf = 0, ff = 0;
+  uint8_t* buf = nullptr;  // device: triples, chunk prefix, tiles
+  uint64_t ntri = 0, ntiles = 0, tri_off = 0, pre_off = 0, tile_off = 0;
+};
+
+// Builds the element list of the update on the host from the plan.
+static dc_status kd_build(dc_tree t, const dc_kick_drift_args* a, std::vector<DevTriple>& tri,
+                          std::vector<uint64_t>& pre, std::vector<DevTile>& tiles) {
+  dc_plan p = t->plan;
+  if (a->type >= p->types.size()) return fail(DC_E_INVAL, "kick-drift: type %u not described", a->type);
+  const TypeDesc& ty = p->types[a->type];
+  const uint32_t fl[3] = {a->x_field, a->v_field, a->f_field};
+  for (int r = 0; r < 3; r++) {
+    if (fl[r] >= ty.fields.size()) return fail(DC_E_INVAL, "kick-drift: field %u of %s", fl[r], ty.name.c_str());
+    if (ty.fields[fl[r]].kind != DC_KIND_F64)
+      return fail(DC_E_INVAL, "kick-drift: field %u of %s is not an FP64 array", fl[r], ty.name.c_str());
+  }
+  if (fl[0] == fl[1] || fl[0] == fl[2] || fl[1] == fl[2]) return fail(DC_E_INVAL, "kick-drift: x, v and f must differ");
+  std::vector<uint8_t> used(p->objs.size(), 0);
+  for (const Obj& o : p->objs) {
+    if (o.kind != DC_KIND_STRUCT || o.type != a->type || o.count == 0) continue;
+    for (uint64_t e = 0; e < o.count; e++) {
+      uint32_t tg[3];
+      int nnull = 0;
+      for (int r = 0; r < 3; r++) {
+        tg[r] = kNone;
+        if (o.sobj != kNone) tg[r] = p->slot_target[p->sobj_pre[o.sobj] + e * ty.order.size() + ty.pos[fl[r]]];
+        nnull += tg[r] == kNone;
+      }
+      if (nnull == 3) continue;
+      if (nnull != 0)
+        return fail(DC_E_INVAL, "kick-drift: element %llu of the %s array at arena offset %llu has a null array",
+                    (unsigned long long)e, ty.name.c_str(), (unsigned long long)o.off);
+      const uint64_t n = p->objs[tg[0]].count;
+      if (p->objs[tg[1]].count != n || p->objs[tg[2]].count != n)
+        return fail(DC_E_INVAL, "kick-drift: element %llu at arena offset %llu has arrays of %llu, %llu, %llu",
+                    (unsigned long long)e, (unsigned long long)o.off, (unsigned long long)n,
+                    (unsigned long long)p->objs[tg[1]].count, (unsigned long long)p->objs[tg[2]].count);
+      for (int r = 0; r < 3; r++) {
+        if (used[tg[r]])
+          return fail(DC_E_CONFLICT, "kick-drift: the array at arena offset %llu serves two elements or roles",
+                      (unsigned long long)p->objs[tg[r]].off);
+        used[tg[r]] = 1;
+      }
+      if (n == 0) continue;
+      tri.push_back({o.off + e * ty.size, n});
+    }
+  }
+  pre.resize(tri.size() + 1);
+  pre[0] = 0;
+  for (size_t i = 0; i < tri.size(); i++) pre[i + 1] = pre[i] + (tri[i].count + 1) / 2;
+  // tiles of at most 4096 chunks and kTileMaxLeaves elements
+  const uint64_t T = 4096, total = pre.back(), ne = tri.size();
+  uint64_t l = 0;
+  for (uint64_t c = 0; c < total;) {
+    while (pre[l + 1] <= c) l++;
+    uint64_t hi = std::min<uint64_t>(c + T, total);
+    hi = std::min<uint64_t>(hi, pre[std::min<uint64_t>(l + kTileMaxLeaves, ne)]);
+    uint64_t lh = l;
+    while (pre[lh + 1] < hi) lh++;
+    DevTile tl{};
+    tl.c_lo = c;
+    tl.c_hi = hi;
+    tl.l_lo = (uint32_t)l;
+    tl.l_hi = (uint32_t)lh;
+    tiles.push_back(tl);
+    c = hi;
+  }
+  return DC_OK;
+}
+
+static dc_status kd_prepare(dc_tree t, const dc_kick_drift_args* a, hipStream_t s, KdTables** out) {
+  KdTables*& kd = t->kd;
+  if (kd && kd->type == a->type && kd->xf == a->x_field && kd->vf == a->v_field && kd->ff == a->f_field) {
+    *out = kd;
+    return DC_OK;
+  }
+  std::vector<DevTriple> tri;
+  std::vector<uint64_t> pre;
+  std::vector<DevTile> tiles;
+  DC_TRY(kd_build(t, a, tri, pre, tiles));
+  if (kd) {
+    DC_HIP(hipStreamSynchronize(s));
+    if (kd->buf) DC_HIP(hipFree(kd->buf));
+    delete kd;
+    kd = nullptr;
+  }
+  KdTables* k = new KdTables();
+  k->type = a->type;
+  k->xf = a->x_field;
+  k->vf = a->v_field;
+  k->ff = a->f_field;
+  k->ntri = tri.size();
+  k->ntiles = tiles.size();
+  k->tri_off = 0;
+  k->pre_off = align_up(sizeof(DevTriple) * tri.size(), 256);
+  k->tile_off = align_up(k->pre_off + 8 * pre.size(), 256);
+  const uint64_t bytes = k->tile_off + sizeof(DevTile) * tiles.size();
+  if (hipMalloc((void**)&k->buf, std::max<uint64_t>(bytes, 256)) != hipSuccess) {
+    delete k;
+    return fail(DC_E_NOMEM, "kick-drift tables: %llu bytes", (unsigned long long)bytes);
+  }
+  std::vector<Piece> pcs;
+  if (!tri.empty()) pcs.push_back({k->tri_off, tri.data(), sizeof(DevTriple) * tri.size()});
+  pcs.push_back({k->pre_off, pre.data(), 8 * pre.size()});
+  if (!tiles.empty()) pcs.push_back({k->tile_off, tiles.data(), sizeof(DevTile) * tiles.size()});
+  dc_status st = upload_pieces(t->ctx, k->buf, bytes, pcs, s);
+  if (st != DC_OK) {
+    (void)hipFree(k->buf);
+    delete k;
+    return st;
+  }
+  kd = k;
+  *out = k;
+  return DC_OK;
+}
+
+void kd_free(dc_tree t) {
+  if (!t->kd) return;
+  if (t->kd->buf) (void)hipFree(t->kd->buf);
+  delete t->kd;
+  t->kd = nullptr;
+}
+
+}  // namespace dc
+
+using namespace dc;
+
+extern "C" {
+
+dc_status dc_run_kick_drift(dc_tree t, const dc_kick_drift_args* a, void* stream) {
+  if (!t || t->released || !a) return fail(DC_E_INVAL, "dc_run_kick_drift: null argument");
+  if (!t->attached) return fail(DC_E_STATE, "dc_run_kick_drift: tree is not attached");
+  DC_HIP(hipSetDevice(t->ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  KdTables* k;
+  DC_TRY(kd_prepare(t, a, s, &k));
+  const TypeDesc& ty = t->plan->types[a->type];
+  KickDriftArgs ka{};
+  ka.tri = (const DevTriple*)(k->buf + k->tri_off);
+  ka.pre = (const uint64_t*)(k->buf + k->pre_off);
+  ka.tiles = (const DevTile*)(k->buf + k->tile_off);
+  ka.ntiles = k->ntiles;
+  ka.x_off = ty.fields[a->x_field].offset;
+  ka.v_off = ty.fields[a->v_field].offset;
+  ka.f_off = ty.fields[a->f_field].offset;
+  ka.dt = a->dt;
+  ka.dt_over_m = a->dt_over_m;
+  hipError_t e = hipSuccess;
+  for (uint32_t it = 0; it < a->steps && e == hipSuccess; it++) e = launch_kick_drift(t->tab, ka, s);
+  if (e != hipSuccess) return fail(DC_E_HIP, "kick-drift launch: %s", hipGetErrorString(e));
+  return DC_OK;
+}
+
+}  // extern "C"

@@ -455,6 +455,7 @@ dc_status dc_tree_release(dc_tree t) {
   if (!t) return fail(DC_E_INVAL, "dc_tree_release: null tree");
   t->released = true;
   if (t->tiles_ev) (void)hipEventDestroy(t->tiles_ev);
+  kd_free(t);
   delete t;
   return DC_OK;
 }

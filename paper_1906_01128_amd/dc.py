@@ -54,6 +54,12 @@ class ScalarRef(ctypes.Structure):
                 ("offset", ctypes.c_uint32), ("bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+class KickDriftArgs(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_uint32), ("x_field", ctypes.c_uint32), ("v_field", ctypes.c_uint32),
+                ("f_field", ctypes.c_uint32), ("steps", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("dt", ctypes.c_double), ("dt_over_m", ctypes.c_double)]
+
+
 class Object(ctypes.Structure):
     _fields_ = [("host_addr", u64), ("offset", u64), ("bytes", u64), ("count", u64), ("kind", u32), ("type_id", u32)]
 
@@ -122,6 +128,7 @@ _SIGS = {
     "dc_chain_copy_back": [vp, vp, u32, vp, ctypes.POINTER(Step), u32, ctypes.POINTER(Chain), vp],
     "dc_scalar_declare": [vp, ctypes.POINTER(ScalarRef), u32, vp, vp],
     "dc_scalar_update": [vp, ctypes.POINTER(ScalarRef), u32, vp, vp],
+    "dc_run_kick_drift": [vp, ctypes.POINTER(KickDriftArgs), vp],
     "dc_run_kernel": [vp, ctypes.POINTER(KernelArgs), vp],
     "dc_out_bytes": [vp, ctypes.POINTER(KernelArgs), ctypes.POINTER(u64)],
     "dc_copy_back": [vp, u32, vp],
@@ -357,6 +364,12 @@ class Tree:
 
     def check(self, stream=None):
         _check(load().dc_tree_check(self.h, _stream_ptr(stream)), "dc_tree_check")
+
+    def kick_drift(self, type_id, x_field, v_field, f_field, dt, dt_over_m, steps=1, stream=None):
+        """v <- fma(f, dt_over_m, v); x <- fma(v, dt, x) per step on every
+        element of struct type `type_id`."""
+        ka = KickDriftArgs(type_id, x_field, v_field, f_field, steps, 0, dt, dt_over_m)
+        _check(load().dc_run_kick_drift(self.h, ctypes.byref(ka), _stream_ptr(stream)), "dc_run_kick_drift")
 
     @staticmethod
     def _scalar_refs(refs):

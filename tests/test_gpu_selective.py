@@ -72,19 +72,19 @@ def test_pointerchain_linear(ctx, k, n, iters):
     assert cc.count == n and cc.kind == "f64"
     torch.cuda.synchronize()
     host_before = np.ctypeslib.as_array((ctypes.c_double * max(n, 1)).from_address(
-        ref.objects()[-1]["host"]))[:n].copy()
+        int(ref.objects()[-1]["host"])))[:n].copy()
     assert np.array_equal(buf[:8 * n].cpu().numpy().view(np.float64), host_before), "leaf transfer"
     cc.run_kernel(iters=iters, a=1.0001, b=-0.5)
     cc.copy_back()
     host_after = np.ctypeslib.as_array((ctypes.c_double * max(n, 1)).from_address(
-        ref.objects()[-1]["host"]))[:n]
+        int(ref.objects()[-1]["host"])))[:n]
     assert np.array_equal(host_after.view(np.uint64), want.view(np.uint64)), "pointerchain result"
 
 
 def test_pointerchain_fp32_wide(ctx):
     from paper_1906_01128_amd import dc
     t = fx.wide(seed=77, f1=4, f2=4, lo=1, hi=3001)
-    chain = [(0, 2), (0, 3), (0, 0)]   # root -> mid[2] -> leaf[3] -> its FP32 array
+    chain = [(0, 2), (0, 2), (0, 0)]   # root -> mid[2] -> leaf[2] -> its FP32 array
     ref = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 0)
     addr, count, kind = ref.resolve_chain(0, chain)
     assert kind == "f32"
