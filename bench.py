@@ -15,7 +15,7 @@ starts. `value` is the algorithmic bytes of a step over its time. The
 host-link part of the deep copy (pack + host-to-device + copy back) is timed
 separately and reported as `host_link` / `end_to_end`, never as `value`.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload linear|wide|batched|served]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload linear|wide|batched|served|sweep]
 """
 import argparse
 import json
@@ -35,7 +35,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="linear", choices=["linear", "wide", "batched", "served", "copycal"])
+    ap.add_argument("--workload", default="linear",
+                    choices=["linear", "wide", "batched", "served", "sweep", "copycal"])
+    ap.add_argument("--full", action="store_true", help="sweep: the paper's full size range")
     ap.add_argument("--passes", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-link", action="store_true", help="skip the host-link measurements")
@@ -327,6 +329,22 @@ def bench_batched(args, torch, dc):
         for k, name in enumerate(("attach", "leaf_tiles", "detach")):
             phases[name].append(e[k].elapsed_time(e[k + 1]))
     tree.check()
+    # the MD kick-drift kernel on the same cells: v += f dt/m, x += v dt
+    tree.attach()
+    dt = 1e-3
+    tree.kick_drift(1, 0, 1, 2, dt, dt / 39.948, steps=1)   # builds the element list
+    kd = []
+    for _ in range(5):
+        e0, e1 = ev(), ev()
+        e0.record(s)
+        tree.kick_drift(1, 0, 1, 2, dt, dt / 39.948, steps=1)
+        e1.record(s)
+        torch.cuda.synchronize()
+        kd.append(e0.elapsed_time(e1) / 1e3)
+    tree.check()
+    tree.detach()
+    kd_bytes = 40 * (info.leaf_bytes // 24)    # per double of x: read x, v, f; write x, v
+    kd_gbps = kd_bytes / pct(kd, 50) / 1e9
     kb = 2 * info.leaf_bytes
     rb = 2 * (info.nslots_nonnull * 16 + info.nslots * 8 + info.nobjects * 16)
     v = (kb + rb) / pct(step_s, 50) / 1e9
@@ -341,6 +359,9 @@ def bench_batched(args, torch, dc):
                          "unit": "GB/s", "frac": round(v / HBM_PEAK_GBPS, 4), "traffic": None},
             "latency_ms": {"p50": round(1e3 * pct(step_s, 50), 3), "p99": round(1e3 * pct(step_s, 99), 3)},
             "separate_launches_ms": {k: round(pct(v_, 50), 3) for k, v_ in phases.items()},
+            "kick_drift": {"kernel": "k_kick_drift", "ms": round(1e3 * pct(kd, 50), 3),
+                           "bytes_per_launch": kd_bytes, "achieved_GBps": round(kd_gbps, 1),
+                           "frac": round(kd_gbps / HBM_PEAK_GBPS, 4)},
             "host": {"plan_s": round(plan_s, 3), "stage_s": round(stage_s, 3),
                      "stage_GBps": round(plan.arena_bytes / stage_s / 1e9, 2)}}
 
@@ -396,6 +417,142 @@ def bench_served(args, torch, dc, njobs=200, bytes_hi=64 << 20, rho=0.8, budget=
                        "admitted_while_busy": st.batches, "peak_bytes": st.peak_bytes, "wall_s": round(wall, 3)}}
 
 
+def _time_marshal(torch, dc, ctx, t, chains, allused, reps):
+    """Marshalling (Algorithm 1): plan the whole tree, pack, copy to the
+    device, relocate; one kernel pass over the used arrays; copy back."""
+    s = torch.cuda.current_stream()
+    rows = []
+    schema = dc.Schema(t.types)
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = dc.Plan(schema, t.root_type, t.roots)
+        arena = torch.empty(max(plan.arena_bytes, 16), dtype=torch.uint8, device="cuda")
+        scratch = torch.empty(max(plan.scratch_bytes, 16), dtype=torch.uint8, device="cuda")
+        t1 = time.perf_counter()
+        tree = dc.Tree(ctx, plan, arena, scratch)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        if allused:
+            tree.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.0)
+        else:
+            for ch in chains:
+                tree.run_kernel(mode="resolved", select="chain", chain=ch, iters=1, a=1.0001, b=0.0)
+        e1.record(s)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        tree.copy_back()
+        t4 = time.perf_counter()
+        rows.append({"plan_ms": 1e3 * (t1 - t0), "h2d_ms": 1e3 * (t2 - t1), "kernel_ms": e0.elapsed_time(e1),
+                     "d2h_ms": 1e3 * (t4 - t3), "wall_ms": 1e3 * (t4 - t0)})
+        tree.release()
+        plan.close()
+        del tree, arena, scratch
+    out = {k: round(pct([r[k] for r in rows], 50), 4) for k in rows[0]}
+    out["bytes_to_device"] = plan.arena_bytes
+    return out
+
+
+def _time_pointerchain(torch, dc, ctx, t, chains, reps):
+    """pointerchain (Section 3): each chain resolved on the host tree and
+    only the array it ends in transferred; one kernel pass per array; copy
+    back into the host arrays."""
+    s = torch.cuda.current_stream()
+    schema = dc.Schema(t.types)
+    rows = []
+    nbytes = 0
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ccs = [dc.ChainCopy(ctx, schema, t.root_type, t.roots[0], ch) for ch in chains]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for cc in ccs:
+            cc.run_kernel(iters=1, a=1.0001, b=0.0)
+        e1.record(s)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for cc in ccs:
+            cc.copy_back()
+        t3 = time.perf_counter()
+        nbytes = sum(cc.count * 8 for cc in ccs)
+        rows.append({"h2d_ms": 1e3 * (t1 - t0), "kernel_ms": e0.elapsed_time(e1), "d2h_ms": 1e3 * (t3 - t2),
+                     "wall_ms": 1e3 * (t3 - t0)})
+        del ccs
+    out = {k: round(pct([r[k] for r in rows], 50), 4) for k in rows[0]}
+    out["bytes_to_device"] = nbytes
+    return out
+
+
+def bench_sweep(args, torch, dc):
+    """The paper's Linear and Dense scenarios (Section 4, Tables 1-2) swept
+    over their parameters, marshalling against pointerchain, wall-clock of
+    the whole program (plan, transfer in, one kernel pass, transfer back)
+    and kernel time. Linear: k levels, n doubles per A array, three layout
+    schemes (allinit-allused, allinit-LLused, LLinit-LLused). Dense: q
+    children per node, depth 3, n doubles per A array; the kernel scales the
+    A array of the last element at every level. Sizes follow equations
+    (1)-(3). The kernel scales by a constant: x = fma(x, 1.0001, 0)."""
+    import math
+    import fixtures as fx
+    fx.set_threads(0)
+    ctx = dc.Context(0)
+    reps = max(1, min(args.steps, 5))
+    ks = [2, 4, 6, 8, 10]
+    ns = [10 ** e for e in range(2, 9 if args.full else 8)]
+    rows = []
+    for k in ks:
+        for n in ns:
+            last = [[(1, 0)] * (k - 1) + [(0, 0)]]
+            every = [[(1, 0)] * lv + [(0, 0)] for lv in range(k)]
+            t_all = fx.linear(seed=fx.SEED_BASE + 100 + k, k=k, n=n, scheme=0)
+            for layout, tree_, chains, allused in (("allinit-allused", t_all, every, True),
+                                                   ("allinit-LLused", t_all, last, False)):
+                m = _time_marshal(torch, dc, ctx, tree_, chains, allused, reps)
+                pc = _time_pointerchain(torch, dc, ctx, tree_, chains, reps)
+                rows.append({"scenario": "linear", "layout": layout, "k": k, "n": n, "marshal": m,
+                             "pointerchain": pc, "wall_ratio": round(m["wall_ms"] / pc["wall_ms"], 3)})
+            del t_all
+            t_ll = fx.linear(seed=fx.SEED_BASE + 200 + k, k=k, n=n, scheme=1)
+            m = _time_marshal(torch, dc, ctx, t_ll, last, False, reps)
+            pc = _time_pointerchain(torch, dc, ctx, t_ll, last, reps)
+            rows.append({"scenario": "linear", "layout": "LLinit-LLused", "k": k, "n": n, "marshal": m,
+                         "pointerchain": pc, "wall_ratio": round(m["wall_ms"] / pc["wall_ms"], 3)})
+            del t_ll
+            log(args, f"linear k={k} n={n} done")
+    for q in (2, 4, 8, 16):
+        for n in (10, 100, 1000, 10 ** 4, 10 ** 5):
+            nodes = sum(q ** lv for lv in range(4))
+            if nodes * 8 * n > (4 << 30 if args.full else 1 << 30):
+                continue
+            t = fx.dense(seed=fx.SEED_BASE + 300 + q, q=q, n=n, D=3, packed_last=0)
+            chains = [[(1, q - 1)] * lv + [(0, 0)] for lv in range(4)]
+            m = _time_marshal(torch, dc, ctx, t, chains, False, reps)
+            pc = _time_pointerchain(torch, dc, ctx, t, chains, reps)
+            rows.append({"scenario": "dense", "layout": "last element of each level", "q": q, "n": n, "D": 3,
+                         "marshal": m, "pointerchain": pc, "wall_ratio": round(m["wall_ms"] / pc["wall_ms"], 3)})
+            del t
+            log(args, f"dense q={q} n={n} done")
+    ratios = [r["wall_ratio"] for r in rows]
+    geo = math.exp(sum(math.log(x) for x in ratios) / len(ratios))
+    big = max((r for r in rows if r["scenario"] == "linear"), key=lambda r: r["marshal"]["bytes_to_device"])
+    kb = 2 * 8 * big["n"] * (big["k"] if big["layout"] == "allinit-allused" else 1)
+    kgb = kb / (big["marshal"]["kernel_ms"] / 1e3) / 1e9
+    return {"metric": "wall-clock of marshalling over pointerchain (geometric mean over the sweep)",
+            "value": round(geo, 3), "unit": "x", "higher_is_better": True, "steps": reps, "dtype": "f64",
+            "config": {"workload": "Linear k in {2,4,6,8,10} x n in 10^2..10^%d x 3 layout schemes; Dense q in "
+                                   "{2,4,8,16} x n in 10..10^5, D=3 (trees above %s skipped)"
+                                   % (8 if args.full else 7, "4 GiB" if args.full else "1 GiB")},
+            "roofline": {"bound": "hbm", "kernel": "k_stream_resolved / k_leaf_tiles (largest Linear row)",
+                         "achieved": round(kgb, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(kgb / HBM_PEAK_GBPS, 4), "traffic": None},
+            "rows": rows}
+
+
 def bench_copycal(args, torch, dc):
     """A plain device-to-device copy of 1 GiB, three times: the reference
     kernel whose FETCH_SIZE / WRITE_SIZE counters calibrate the HBM traffic
@@ -437,6 +594,8 @@ def main():
         out = bench_batched(args, torch, dc)
     elif args.workload == "copycal":
         out = bench_copycal(args, torch, dc)
+    elif args.workload == "sweep":
+        out = bench_sweep(args, torch, dc)
     else:
         out = bench_served(args, torch, dc)
     out.setdefault("n_gpus", 1)

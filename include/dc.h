@@ -218,6 +218,10 @@ dc_status dc_resolve_chain(dc_tree tree, uint64_t root_index, const dc_step* ste
  * the count and the kind. Returns once the host array has been read.
  * Errors: DC_E_INVAL (bad field or steps), DC_E_RANGE (null before the end,
  * index past an array, buffer too small). */
+/* The count and kind of the host array a chain ends in (out->dev_addr = 0),
+ * so that the caller can size d_buf. Needs no device. Errors as below. */
+dc_status dc_chain_query(dc_schema schema, uint32_t root_type, const void* root, const dc_step* steps,
+                         uint32_t nsteps, dc_chain* out);
 dc_status dc_chain_to_device(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* root, const dc_step* steps,
                              uint32_t nsteps, void* d_buf, uint64_t buf_bytes, void* stream, dc_chain* out);
 /* `iters` passes of x = fma(x, a, b) (FP64: a, b; FP32: af, bf) over an array

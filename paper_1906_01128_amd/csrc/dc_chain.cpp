@@ -70,6 +70,19 @@ using namespace dc;
 
 extern "C" {
 
+dc_status dc_chain_query(dc_schema schema, uint32_t root_type, const void* root, const dc_step* steps,
+                         uint32_t nsteps, dc_chain* out) {
+  if (!out) return fail(DC_E_INVAL, "dc_chain_query: null argument");
+  uint64_t addr, count;
+  uint32_t kind;
+  DC_TRY(host_chain(schema, root_type, root, steps, nsteps, &addr, &count, &kind));
+  out->dev_addr = 0;
+  out->count = count;
+  out->kind = kind;
+  out->reserved = 0;
+  return DC_OK;
+}
+
 dc_status dc_chain_to_device(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* root, const dc_step* steps,
                              uint32_t nsteps, void* d_buf, uint64_t buf_bytes, void* stream, dc_chain* out) {
   if (!ctx || !out || !d_buf) return fail(DC_E_INVAL, "dc_chain_to_device: null argument");

@@ -122,6 +122,7 @@ _SIGS = {
     "dc_attach": [vp, vp],
     "dc_detach": [vp, vp],
     "dc_resolve_chain": [vp, u64, ctypes.POINTER(Step), u32, vp, ctypes.POINTER(Chain)],
+    "dc_chain_query": [vp, u32, vp, ctypes.POINTER(Step), u32, ctypes.POINTER(Chain)],
     "dc_chain_to_device": [vp, vp, u32, vp, ctypes.POINTER(Step), u32, vp, u64, vp, ctypes.POINTER(Chain)],
     "dc_chain_run_kernel": [vp, ctypes.POINTER(Chain), u32, ctypes.c_double, ctypes.c_double, ctypes.c_float,
                             ctypes.c_float, vp],
@@ -424,14 +425,31 @@ class Tree:
             pass
 
 
+ELEM_BYTES = {1: 4, 2: 8, 3: 4, 4: 8, 5: 1}
+
+
+def chain_query(schema: Schema, root_type: int, root: int, chain) -> Chain:
+    """Count and kind of the host array a chain ends in."""
+    c = Chain()
+    _check(load().dc_chain_query(schema.h, root_type, root, steps_array(chain), len(chain), ctypes.byref(c)),
+           "dc_chain_query")
+    return c
+
+
 class ChainCopy:
     """The pointerchain transfer scheme: only the array at the end of a chain
     is copied to the device (into `buf`, a torch uint8 device tensor)."""
 
-    def __init__(self, ctx: Context, schema: Schema, root_type: int, root: int, chain, buf, stream=None):
-        self.ctx, self.schema, self.root_type, self.root, self.buf = ctx, schema, root_type, root, buf
+    def __init__(self, ctx: Context, schema: Schema, root_type: int, root: int, chain, buf=None, stream=None):
+        """buf None: a device buffer of the array's size is allocated here."""
         self._steps = steps_array(chain)
         self._n = len(chain)
+        if buf is None:
+            q = chain_query(schema, root_type, root, chain)
+            import torch
+            buf = torch.empty(max(16, (q.count * ELEM_BYTES[q.kind] + 15) // 16 * 16), dtype=torch.uint8,
+                              device="cuda")
+        self.ctx, self.schema, self.root_type, self.root, self.buf = ctx, schema, root_type, root, buf
         self.c = Chain()
         _check(load().dc_chain_to_device(ctx.h, schema.h, root_type, root, self._steps, self._n, _dev_ptr(buf),
                                          buf.numel(), _stream_ptr(stream), ctypes.byref(self.c)),

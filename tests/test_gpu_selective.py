@@ -117,3 +117,60 @@ def test_pointerchain_errors(ctx):
         dc.ChainCopy(ctx, schema, 0, t.roots[0], [(1, 0), (1, 0), (0, 0)], buf[8:])
     cc = dc.ChainCopy(ctx, schema, 0, t.roots[0], [(1, 0), (1, 0), (0, 0)], buf)
     assert cc.count == 100
+
+
+# ---- the sweep's configurations: Dense chains and Linear allinit -----------------------
+
+
+@pytest.mark.parametrize("q,n", [(2, 10), (3, 7), (4, 1000)])
+def test_dense_marshal_and_pointerchain(ctx, q, n):
+    """The Dense kernel scales the A array of the last element at every level:
+    through the marshalled tree and through pointerchain transfers."""
+    from paper_1906_01128_amd import dc
+    t = fx.dense(seed=fx.SEED_BASE + 300 + q, q=q, n=n, D=3, packed_last=0)
+    chains = [[(1, q - 1)] * lv + [(0, 0)] for lv in range(4)]
+    c = Copy(ctx, t)
+    for ch in chains:
+        c.tree.run_kernel(mode="resolved", select="chain", chain=ch, iters=1, a=1.0001, b=0.0)
+        c.oracle.run_kernel(1.0001, 0.0, iters=1, select="leaf", chain=ch)
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "dense marshalled")
+    # pointerchain on a second copy of the same tree
+    t2 = fx.dense(seed=fx.SEED_BASE + 300 + q, q=q, n=n, D=3, packed_last=0)
+    ref = orc.OracleCopy(t2.types, t2.root_type, t2.roots, 64, 0)
+    schema = dc.Schema(t2.types)
+    ccs = [dc.ChainCopy(ctx, schema, 0, t2.roots[0], ch) for ch in chains]
+    for cc, ch in zip(ccs, chains):
+        assert cc.count == n
+        cc.run_kernel(iters=1, a=1.0001, b=0.0)
+        cc.copy_back()
+        addr, count, _ = ref.resolve_chain(0, ch)
+        before = ref.arena()[addr:addr + 8 * count].copy()
+        ref.run_kernel(1.0001, 0.0, iters=1, select="leaf", chain=ch)
+        want = ref.arena()[addr:addr + 8 * count]
+        host = next(int(o["host"]) for o in ref.objects() if int(o["off"]) == addr)
+        got = np.ctypeslib.as_array((ctypes.c_uint8 * max(1, 8 * count)).from_address(host))[:8 * count]
+        assert np.array_equal(got, want) and not np.array_equal(got, before)
+
+
+def test_linear_allinit_allused_both_schemes(ctx):
+    from paper_1906_01128_amd import dc
+    k, n = 6, 3001
+    t = fx.linear(seed=fx.SEED_BASE + 104, k=k, n=n, scheme=0)
+    c = Copy(ctx, t)
+    c.tree.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.0)
+    c.oracle.run_kernel(1.0001, 0.0, iters=1, select="all")
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "allinit-allused marshalled")
+    c.tree.copy_back()
+    # the host arrays now hold one pass; pointerchain adds a second to each
+    schema = dc.Schema(t.types)
+    chains = [[(1, 0)] * lv + [(0, 0)] for lv in range(k)]
+    for ch in chains:
+        cc = dc.ChainCopy(ctx, schema, 0, t.roots[0], ch)
+        cc.run_kernel(iters=1, a=1.0001, b=0.0)
+        cc.copy_back()
+    c.oracle.run_kernel(1.0001, 0.0, iters=1, select="all")
+    for o in c.oracle.objects():
+        if o["kind"] == 2:
+            got = np.ctypeslib.as_array((ctypes.c_uint8 * int(o["bytes"])).from_address(int(o["host"])))
+            want = c.oracle.arena()[int(o["off"]): int(o["off"]) + int(o["bytes"])]
+            assert np.array_equal(got, want)
