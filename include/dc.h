@@ -347,14 +347,17 @@ typedef struct {
   uint32_t block;          /* threads per workgroup: 256, 512 or 1024 */
   uint32_t wg_per_cu;      /* resident workgroups per compute unit */
   uint32_t tile_chunks;    /* 16-byte chunks per compute tile */
-  uint32_t reserved;
+  uint32_t launches;       /* 0: one persistent launch; 1: three ordinary launches
+                              (relocate, every leaf, reverse relocate), for which
+                              block and wg_per_cu are not used */
 } dc_tune;
 
 enum { DC_BATCH_ATTACH = 1, DC_BATCH_DETACH = 2 };
 /* Every structure's relocation and its leaves' kernel (args: RESOLVED,
- * ALL_LEAVES, iters == 1) in one persistent launch: workgroups take
- * relocation units, then compute tiles, then (DETACH) reverse relocation
- * units from one device work queue. ATTACH requires a staged (unrelocated)
+ * ALL_LEAVES, iters == 1). tune->launches 0: one persistent launch whose
+ * workgroups take relocation units, then compute tiles, then (DETACH)
+ * reverse relocation units from one device work queue; 1: the same work as
+ * three stream-ordered launches. ATTACH requires a staged (unrelocated)
  * tree; DETACH leaves it staged again. tune NULL: the cached autotuner choice
  * or defaults. Asynchronous on `stream`. */
 dc_status dc_batch_run(dc_tree tree, const dc_kernel_args* args, const dc_tune* tune, uint32_t flags, void* stream);

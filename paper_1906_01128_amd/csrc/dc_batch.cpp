@@ -1,5 +1,6 @@
-// libdc batched form: one persistent relocate+compute launch over every
-// structure of a plan, its capture in a HIP graph, and the tile autotuner.
+// libdc batched form: relocation and the leaf kernel of every structure of a
+// plan, as one persistent launch or as three ordinary ones, its capture in a
+// HIP graph, and the autotuner that picks between the shapes.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -13,9 +14,10 @@
 
 namespace dc {
 
-static const dc_tune kDefaultTune = {256, 4, 16384, 0};
+static const dc_tune kDefaultTune = {256, 4, 1024, 0};
 
 static dc_status check_tune(const dc_tune& t) {
+  if (t.launches > 1) return fail(DC_E_INVAL, "tune.launches %u (0 or 1)", t.launches);
   if (t.block != 256 && t.block != 512 && t.block != 1024) return fail(DC_E_INVAL, "tune.block %u", t.block);
   if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return fail(DC_E_INVAL, "tune.wg_per_cu %u", t.wg_per_cu);
   if (t.tile_chunks < kTileMinChunks || t.tile_chunks > kTileMaxChunks || (t.tile_chunks & (t.tile_chunks - 1)))
@@ -62,8 +64,8 @@ static bool cache_lookup(const std::string& key, dc_tune* out) {
   while (fgets(line, sizeof(line), f)) {
     char k[200];
     dc_tune tu{};
-    if (sscanf(line, "{\"key\": \"%199[^\"]\", \"block\": %u, \"wg_per_cu\": %u, \"tile_chunks\": %u}", k, &tu.block,
-               &tu.wg_per_cu, &tu.tile_chunks) == 4 &&
+    if (sscanf(line, "{\"key\": \"%199[^\"]\", \"block\": %u, \"wg_per_cu\": %u, \"tile_chunks\": %u, \"launches\": %u",
+               k, &tu.block, &tu.wg_per_cu, &tu.tile_chunks, &tu.launches) == 5 &&
         key == k && check_tune(tu) == DC_OK) {
       *out = tu;
       found = true;  // the last entry wins
@@ -80,8 +82,8 @@ static void cache_store(const std::string& key, const dc_tune& tu, double us) {
   if (slash != std::string::npos) mkdir(path.substr(0, slash).c_str(), 0755);  // may already exist
   FILE* f = fopen(path.c_str(), "a");
   if (!f) return;
-  fprintf(f, "{\"key\": \"%s\", \"block\": %u, \"wg_per_cu\": %u, \"tile_chunks\": %u, \"us\": %.1f}\n", key.c_str(),
-          tu.block, tu.wg_per_cu, tu.tile_chunks, us);
+  fprintf(f, "{\"key\": \"%s\", \"block\": %u, \"wg_per_cu\": %u, \"tile_chunks\": %u, \"launches\": %u, \"us\": %.1f}\n",
+          key.c_str(), tu.block, tu.wg_per_cu, tu.tile_chunks, tu.launches, us);
   fclose(f);
 }
 
@@ -118,10 +120,16 @@ static dc_status enqueue_batch(dc_tree t, const LeafArgs& la, const dc_tune& tu,
                                bool capturing = false) {
   dc_plan p = t->plan;
   if (!p->leaves.empty() && !capturing) DC_TRY(tree_ensure_tiles(t, tu.tile_chunks, s));
-  hipError_t e = launch_reset_counters(t->tab.hdr, s);
-  if (e == hipSuccess) {
-    const uint64_t ntiles = p->leaves.empty() ? 0 : t->ntiles;
-    e = launch_batch(t->tab, la, flags, tu.block, (uint32_t)t->ctx->ncu * tu.wg_per_cu, ntiles, s);
+  const uint64_t ntiles = p->leaves.empty() ? 0 : t->ntiles;
+  hipError_t e = hipSuccess;
+  if (tu.launches == 1) {
+    // the same work as three ordinary launches: relocate, every leaf, reverse
+    if (flags & DC_BATCH_ATTACH) e = launch_relocate(t->tab, true, s);
+    if (e == hipSuccess) e = launch_leaf_tiles(t->tab, la, ntiles, false, s);
+    if (e == hipSuccess && (flags & DC_BATCH_DETACH)) e = launch_relocate(t->tab, false, s);
+  } else {
+    e = launch_reset_counters(t->tab.hdr, s);
+    if (e == hipSuccess) e = launch_batch(t->tab, la, flags, tu.block, (uint32_t)t->ctx->ncu * tu.wg_per_cu, ntiles, s);
   }
   if (e != hipSuccess) return fail(DC_E_HIP, "batch launch: %s", hipGetErrorString(e));
   return DC_OK;
@@ -177,11 +185,12 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
   const uint32_t flags = DC_BATCH_ATTACH | DC_BATCH_DETACH;
   std::vector<dc_tune> cands;
   for (uint32_t block : {256u, 512u})
-    for (uint32_t tile : {4096u, 16384u, 65536u})
+    for (uint32_t tile : {1024u, 4096u, 16384u})
       for (uint32_t wg : {2u, 4u, 8u}) {
         dc_tune c{block, wg, tile, 0};
         if (check_tune(c) == DC_OK) cands.push_back(c);
       }
+  for (uint32_t tile : {1024u, 2048u, 4096u}) cands.push_back(dc_tune{256, 1, tile, 1});
   clear_error();
   dc_tune best = kDefaultTune;
   double best_us = 1e300;

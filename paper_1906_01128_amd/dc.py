@@ -80,7 +80,7 @@ class KernelArgs(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("block", u32), ("wg_per_cu", u32), ("tile_chunks", u32), ("reserved", u32)]
+    _fields_ = [("block", u32), ("wg_per_cu", u32), ("tile_chunks", u32), ("launches", u32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -408,7 +408,8 @@ class Tree:
         ka = _kargs(mode="resolved", select="all", iters=1, a=a, b=b)
         tu = Tune()
         _check(load().dc_autotune(self.h, ctypes.byref(ka), reps, ctypes.byref(tu)), "dc_autotune")
-        return {"block": tu.block, "wg_per_cu": tu.wg_per_cu, "tile_chunks": tu.tile_chunks}
+        return {"block": tu.block, "wg_per_cu": tu.wg_per_cu, "tile_chunks": tu.tile_chunks,
+                "launches": tu.launches}
 
     def graph(self, a=1.0001, b=0.5, tune=None, upload=False, download=False, out=None) -> "Graph":
         return Graph(self, a, b, tune, upload, download, out)
@@ -481,6 +482,7 @@ def _tune(tune):
     tu.block = tune.get("block", 0)
     tu.wg_per_cu = tune.get("wg_per_cu", 0)
     tu.tile_chunks = tune.get("tile_chunks", 0)
+    tu.launches = tune.get("launches", 0)
     return tu
 
 

@@ -43,7 +43,8 @@ def test_batch_md_attach(ctx):
 @pytest.mark.parametrize("tune", [None, dict(block=256, wg_per_cu=2, tile_chunks=1024),
                                   dict(block=512, wg_per_cu=8, tile_chunks=4096),
                                   dict(block=1024, wg_per_cu=1, tile_chunks=65536),
-                                  dict(block=256, wg_per_cu=4, tile_chunks=1 << 20)])
+                                  dict(block=256, wg_per_cu=4, tile_chunks=1 << 20),
+                                  dict(tile_chunks=1024, launches=1), dict(tile_chunks=4096, launches=1)])
 def test_batch_attach_detach_any_tile_shape(ctx, tune):
     t = fx.md(seed=5, nsims=60, cells_lo=1, cells_hi=40, mean_atoms=5)
     c = Copy(ctx, t, relocate=False)
@@ -66,10 +67,11 @@ def test_batch_wide_and_out_of_place(ctx):
     assert_same_bytes(c.device_arena(), c.oracle.arena(), "arena relocated, leaves untouched")
 
 
-def test_graph_replays(ctx):
+@pytest.mark.parametrize("launches", [0, 1])
+def test_graph_replays(ctx, launches):
     t = fx.md(seed=6, nsims=40, cells_lo=2, cells_hi=30, mean_atoms=8)
     c = Copy(ctx, t, relocate=False)
-    g = c.tree.graph(a=1.0001, b=0.5)
+    g = c.tree.graph(a=1.0001, b=0.5, tune=dict(tile_chunks=1024, launches=launches))
     x = torch.ones(1 << 20, device="cuda")
     for r in range(1, 4):
         g.launch()
@@ -98,7 +100,7 @@ def test_autotune_then_parity(ctx, tmp_path, monkeypatch):
     t = fx.md(seed=8, nsims=200, cells_lo=4, cells_hi=64, mean_atoms=16)
     c = Copy(ctx, t, relocate=False)
     choice = c.tree.autotune(reps=1)
-    assert choice["block"] in (256, 512, 1024)
+    assert choice["block"] in (256, 512, 1024) and choice["launches"] in (0, 1)
     assert (tmp_path / "tune.json").exists()
     # the autotuner changed leaf values; copy again and run with the cached choice
     t2 = fx.md(seed=8, nsims=200, cells_lo=4, cells_hi=64, mean_atoms=16)
