@@ -30,6 +30,24 @@ HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E
 LINK_PEAK_GBPS = 63.0       # PCIe Gen5 x16 per direction after encoding (32 GT/s x16 on the box)
 
 
+def traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` measured by rocprofv3 counters
+    (profiles/hbm_counters.txt), or None when there is no entry or the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        src = open(os.path.join(ROOT, "paper_1906_01128_amd", "csrc", "dc_kernels.hip"), "rb").read()
+        lines = open(os.path.join(ROOT, "profiles", "hbm_counters.txt")).read().splitlines()
+    except OSError:
+        return None
+    sha = hashlib.sha256(src).hexdigest()
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 6 and not ln.startswith("#") and f[0] == workload and f[1] == kernel and f[2] == sha:
+            return int(f[5])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,7 +191,8 @@ def bench_linear(args, torch, dc):
                    "k": 8, "n": 1 << 24, "passes": P, "leaf_bytes": leaf, "arena_bytes": plan.arena_bytes},
         "roofline": {"bound": "hbm", "kernel": f"k_stream_{'deref' if dominant == 'deref_each' else 'resolved'}",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic("linear", "k_stream_deref" if dominant == "deref_each" else "k_stream_resolved"),
                      "bytes_per_launch": 2 * leaf, "avg_launch_us": round(dom_t * 1e6, 3)},
         "latency_ms": {"p50": round(1e3 * pct(step_s, 50), 4), "p99": round(1e3 * pct(step_s, 99), 4)},
         "modes": {"resolved_GBps": round(res_gbps, 1), "deref_each_GBps": round(der_gbps, 1),
@@ -254,7 +273,8 @@ def bench_wide(args, torch, dc, hi=65536):
                       "leaf_bytes": info.leaf_bytes, "arena_bytes": plan.arena_bytes, "nleaves": info.nleaves},
            "roofline": {"bound": "hbm", "kernel": "k_leaf_tiles", "achieved": round(kb / pct(ker_s, 50) / 1e9, 1),
                         "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                        "frac": round(kb / pct(ker_s, 50) / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None},
+                        "frac": round(kb / pct(ker_s, 50) / 1e9 / HBM_PEAK_GBPS, 4),
+                        "traffic": traffic("wide", "k_leaf_tiles")},
            "relocation_us_p50": round(1e6 * pct(rel_s, 50), 2),
            "latency_ms": {"p50": round(1e3 * pct(step_s, 50), 4), "p99": round(1e3 * pct(step_s, 99), 4)}}
     if not args.no_link:
@@ -349,6 +369,13 @@ def bench_batched(args, torch, dc):
     kb = 2 * info.leaf_bytes
     rb = 2 * (info.nslots_nonnull * 16 + info.nslots * 8 + info.nobjects * 16)
     v = (kb + rb) / pct(step_s, 50) / 1e9
+    kname = "k_leaf_tiles" if (tune or {"launches": 1}).get("launches") else "k_batch"
+    if kname == "k_leaf_tiles":   # the compute launch of the graph, timed as a separate launch
+        k_s = pct(phases["leaf_tiles"], 50) / 1e3
+        k_ach = kb / k_s / 1e9
+    else:                         # one persistent launch does the whole step
+        k_s = pct(step_s, 50)
+        k_ach = v
     return {"metric": "deep-copy+kernel effective GB/s vs HBM/link roofline; p50/p99 latency",
             "value": round(v, 2), "unit": "GB/s", "ms_per_step": round(1e3 * pct(step_s, 50), 3),
             "steps": args.steps, "dtype": "f64",
@@ -357,14 +384,14 @@ def bench_batched(args, torch, dc):
                                    "(one persistent launch or three launches, as the autotuner picks)",
                        "objects": info.nobjects, "slots": info.nslots_nonnull, "leaf_bytes": info.leaf_bytes,
                        "arena_bytes": plan.arena_bytes, "tune": tune},
-            "roofline": {"bound": "hbm", "kernel": "k_leaf_tiles" if tune and tune.get("launches") else "k_batch",
-                         "achieved": round(v, 1), "peak": HBM_PEAK_GBPS,
-                         "unit": "GB/s", "frac": round(v / HBM_PEAK_GBPS, 4), "traffic": None},
+            "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(k_ach, 1), "peak": HBM_PEAK_GBPS,
+                         "unit": "GB/s", "frac": round(k_ach / HBM_PEAK_GBPS, 4), "traffic": traffic("batched", kname),
+                         "avg_launch_us": round(1e6 * k_s, 1)},
             "latency_ms": {"p50": round(1e3 * pct(step_s, 50), 3), "p99": round(1e3 * pct(step_s, 99), 3)},
             "separate_launches_ms": {k: round(pct(v_, 50), 3) for k, v_ in phases.items()},
             "kick_drift": {"kernel": "k_kick_drift", "ms": round(1e3 * pct(kd, 50), 3),
                            "bytes_per_launch": kd_bytes, "achieved_GBps": round(kd_gbps, 1),
-                           "frac": round(kd_gbps / HBM_PEAK_GBPS, 4)},
+                           "frac": round(kd_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic("batched", "k_kick_drift")},
             "host": {"plan_s": round(plan_s, 3), "stage_s": round(stage_s, 3),
                      "stage_GBps": round(plan.arena_bytes / stage_s / 1e9, 2)}}
 

@@ -14,7 +14,7 @@
 
 namespace dc {
 
-static const dc_tune kDefaultTune = {256, 4, 1024, 0};
+static const dc_tune kDefaultTune = {256, 4, 1024, 1};
 
 static dc_status check_tune(const dc_tune& t) {
   if (t.launches > 1) return fail(DC_E_INVAL, "tune.launches %u (0 or 1)", t.launches);
