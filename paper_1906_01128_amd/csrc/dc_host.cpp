@@ -1,4 +1,7 @@
 // libdc host core: errors, thread pool, context and pinned staging, schema.
+#include <sched.h>
+#include <stdlib.h>
+
 #include "dc_host.h"
 
 #include <stdarg.h>
@@ -50,13 +53,27 @@ void Pool::loop() {
       seen = gen_;
       fn = fn_;
       n = n_;
-      active_++;
     }
-    for (int i; (i = next_.fetch_add(1)) < n;) (*fn)(i);
-    {
+    work(seen, fn, n);
+  }
+}
+
+// Claims and runs items of generation g until none is left. A claim is a
+// compare-and-swap on (generation, next index), so a worker that woke for an
+// older generation can never take an item of a newer one (whose function it
+// does not hold), and the caller's function outlives every item it hands out.
+void Pool::work(uint64_t g, const std::function<void(int)>* fn, int n) {
+  const uint64_t tag = (g & 0xffffffffull) << 32;
+  uint64_t t = ticket_.load();
+  for (;;) {
+    if ((t & ~0xffffffffull) != tag || (int64_t)(t & 0xffffffffull) >= n) return;
+    if (!ticket_.compare_exchange_weak(t, t + 1)) continue;  // t now holds the current value
+    (*fn)((int)(t & 0xffffffffull));
+    if (done_.fetch_add(1) + 1 == n) {
       std::lock_guard<std::mutex> lk(mu_);
-      if (--active_ == 0) done_cv_.notify_all();
+      done_cv_.notify_all();
     }
+    t = ticket_.load();
   }
 }
 
@@ -66,17 +83,19 @@ void Pool::run(int n, const std::function<void(int)>& fn) {
     for (int i = 0; i < n; i++) fn(i);
     return;
   }
+  uint64_t g;
   {
     std::lock_guard<std::mutex> lk(mu_);
     fn_ = &fn;
     n_ = n;
-    next_.store(0);
-    gen_++;
+    g = ++gen_;
+    done_.store(0);
+    ticket_.store((g & 0xffffffffull) << 32);
   }
   cv_.notify_all();
-  for (int i; (i = next_.fetch_add(1)) < n;) fn(i);
+  work(g, &fn, n);
   std::unique_lock<std::mutex> lk(mu_);
-  done_cv_.wait(lk, [&] { return active_ == 0 && next_.load() >= n; });
+  done_cv_.wait(lk, [&] { return done_.load() >= n; });
   fn_ = nullptr;
 }
 
@@ -188,6 +207,18 @@ const char* dc_last_error(void) { return dc::g_err.c_str(); }
 
 const char* dc_version(void) { return "libdc 0.1 (gfx950)"; }
 
+// Threads for packing and scattering: the CPUs this process may run on,
+// capped by OMP_NUM_THREADS when that is set and by 32.
+static int host_threads() {
+  int n = 0;
+  cpu_set_t set;
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) n = CPU_COUNT(&set);
+  if (n <= 0) n = (int)std::thread::hardware_concurrency();
+  const char* omp = getenv("OMP_NUM_THREADS");
+  if (omp && atoi(omp) > 0) n = std::min(n, atoi(omp));
+  return std::max(1, std::min(n, 32));
+}
+
 dc_status dc_ctx_create(int device, dc_ctx* out) {
   if (!out) return fail(DC_E_INVAL, "dc_ctx_create: out is null");
   *out = nullptr;
@@ -215,8 +246,7 @@ dc_status dc_ctx_create(int device, dc_ctx* out) {
     dc_ctx_destroy(c);
     return fail(DC_E_NOMEM, "dc_ctx_create: device header");
   }
-  unsigned hw = std::thread::hardware_concurrency();
-  c->pool = new Pool((int)std::max(1u, std::min(hw ? hw : 1u, 32u)));
+  c->pool = new Pool(host_threads());
   *out = c;
   clear_error();
   return DC_OK;

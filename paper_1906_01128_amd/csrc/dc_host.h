@@ -46,13 +46,14 @@ class Pool {
 
  private:
   void loop();
+  void work(uint64_t g, const std::function<void(int)>* fn, int n);
   std::vector<std::thread> workers_;
   std::mutex mu_;
   std::condition_variable cv_, done_cv_;
   const std::function<void(int)>* fn_ = nullptr;
   int n_ = 0;
-  std::atomic<int> next_{0};
-  int active_ = 0;
+  std::atomic<uint64_t> ticket_{0};  // (generation << 32) | next item
+  std::atomic<int> done_{0};         // items of the current generation finished
   uint64_t gen_ = 0;
   bool stop_ = false;
 };
