@@ -18,10 +18,13 @@ separately and reported as `host_link` / `end_to_end`, never as `value`.
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload linear|wide|batched|served|sweep]
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -54,8 +57,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="linear",
-                    choices=["linear", "wide", "batched", "served", "sweep", "copycal"])
-    ap.add_argument("--full", action="store_true", help="sweep: the paper's full size range")
+                    choices=["linear", "plain", "wide", "batched", "served", "sweep", "copycal"])
+    ap.add_argument("--full", action="store_true",
+                    help="sweep: the paper's full size range; served: 2000 jobs, leaves up to 256 MiB")
     ap.add_argument("--passes", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-link", action="store_true", help="skip the host-link measurements")
@@ -201,6 +205,34 @@ def bench_linear(args, torch, dc):
         "wall_s": round(wall, 3),
     }
 
+    # single passes with the 256 MB Infinity Cache flushed before each: a
+    # 512 MiB fill between passes evicts the 128 MiB leaf
+    tree.attach()
+    addr, count, kind = tree.resolve_chain(chain)
+    ch = dc.Chain(addr, count, dc.KIND[kind], 0)
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    fl = {"resolved": [], "deref_each": []}
+    for r in range(2 * 10):
+        mode = "resolved" if r % 2 == 0 else "deref_each"
+        flush.fill_(r & 0xFF)
+        e0, e1 = ev(), ev()
+        e0.record(s)
+        if mode == "resolved":   # the resolved address, no resolve kernel in the pass
+            dc._check(dc.load().dc_chain_run_kernel(ctx.h, ctypes.byref(ch), 1, 1.0001, 0.5,
+                                                    float(np.float32(1.0001)), 0.5, s.cuda_stream),
+                      "dc_chain_run_kernel")
+        else:
+            tree.run_kernel(mode="deref_each", select="chain", chain=chain, iters=1, a=1.0001, b=0.5)
+        e1.record(s)
+        torch.cuda.synchronize()
+        fl[mode].append(e0.elapsed_time(e1) / 1e3)
+    tree.check()
+    tree.detach()
+    del flush
+    out["mall_flushed"] = {"what": "one pass after a 512 MiB fill (Infinity Cache evicted), median of 10",
+                           "resolved_GBps": round(2 * leaf / pct(fl["resolved"], 50) / 1e9, 1),
+                           "deref_each_GBps": round(2 * leaf / pct(fl["deref_each"], 50) / 1e9, 1)}
+
     if not args.no_link:
         # the host-link part: pack + host-to-device + relocation, then copy back
         h2d, d2h, e2e = [], [], []
@@ -233,7 +265,17 @@ def bench_linear(args, torch, dc):
     return out
 
 
-def bench_wide(args, torch, dc, hi=65536):
+def bench_wide(args, torch, dc):
+    """The wide tree at its stated parameters (leaf lengths up to 65536,
+    ~0.28 GB) and the wide-1G variant (up to 2^18, ~0.93 GB)."""
+    out = _bench_wide(args, torch, dc, 65536)
+    big = _bench_wide(args, torch, dc, 1 << 18)
+    out["wide_1g"] = {k: big[k] for k in ("value", "ms_per_step", "config", "roofline", "relocation_us_p50",
+                                           "host_link") if k in big}
+    return out
+
+
+def _bench_wide(args, torch, dc, hi):
     """The wide tree (64 x 64 leaves, lengths log-uniform 256..hi, FP32 and
     FP64): step = attach + one fma pass over every leaf + detach."""
     import fixtures as fx
@@ -274,7 +316,7 @@ def bench_wide(args, torch, dc, hi=65536):
            "roofline": {"bound": "hbm", "kernel": "k_leaf_tiles", "achieved": round(kb / pct(ker_s, 50) / 1e9, 1),
                         "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                         "frac": round(kb / pct(ker_s, 50) / 1e9 / HBM_PEAK_GBPS, 4),
-                        "traffic": traffic("wide", "k_leaf_tiles")},
+                        "traffic": traffic("wide" if hi == 65536 else f"wide_hi{hi}", "k_leaf_tiles")},
            "relocation_us_p50": round(1e6 * pct(rel_s, 50), 2),
            "latency_ms": {"p50": round(1e3 * pct(step_s, 50), 4), "p99": round(1e3 * pct(step_s, 99), 4)}}
     if not args.no_link:
@@ -286,14 +328,51 @@ def bench_wide(args, torch, dc, hi=65536):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             tr.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.5)
-            tr.copy_back()
+            torch.cuda.synchronize()
             t2 = time.perf_counter()
+            tr.copy_back()
+            t3 = time.perf_counter()
             tr.release()
-            ts.append((t1 - t0, t2 - t1))
-        h2d = plan.arena_bytes / min(a for a, _ in ts) / 1e9
+            ts.append((t1 - t0, t2 - t1, t3 - t2))
+        h2d = plan.arena_bytes / min(a for a, _, _ in ts) / 1e9
+        d2h = info.leaf_bytes / min(c for _, _, c in ts) / 1e9
         out["host_link"] = {"h2d_GBps": round(h2d, 2), "h2d_frac_of_spec": round(h2d / LINK_PEAK_GBPS, 4),
-                            "end_to_end_ms_p50": round(1e3 * pct([a + b for a, b in ts], 50), 3)}
+                            "d2h_GBps": round(d2h, 2), "d2h_frac_of_spec": round(d2h / LINK_PEAK_GBPS, 4),
+                            "end_to_end_ms_p50": round(1e3 * pct([a + b + c for a, b, c in ts], 50), 3)}
     return out
+
+
+def bench_plain(args, torch, dc, reps=1000):
+    """The plain structure (root -> 16 children -> 1024 FP64 each): the whole
+    job, host tree in and host tree out (pack + H2D + attach + one fma pass
+    over every leaf + copy back), 1000 times. Launch- and latency-bound: 131 KB
+    of payload; the plan is made once and reused, as for repeated copies of
+    one shape."""
+    import fixtures as fx
+    t = fx.plain()
+    ctx = dc.Context(0)
+    plan = dc.Plan(dc.Schema(t.types), t.root_type, t.roots)
+    info = plan.info()
+    arena = torch.empty(plan.arena_bytes, dtype=torch.uint8, device="cuda")
+    scratch = torch.empty(plan.scratch_bytes, dtype=torch.uint8, device="cuda")
+    lat = []
+    for r in range(reps + 20):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tree = dc.Tree(ctx, plan, arena, scratch)
+        tree.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.5)
+        tree.copy_back()
+        t1 = time.perf_counter()
+        tree.release()
+        if r >= 20:
+            lat.append(t1 - t0)
+    job = info.payload_bytes + info.leaf_bytes + 2 * info.leaf_bytes
+    return {"metric": "deep-copy+kernel effective GB/s vs HBM/link roofline; p50/p99 latency",
+            "value": round(job / pct(lat, 50) / 1e9, 3), "unit": "GB/s", "steps": reps, "dtype": "f64",
+            "config": {"workload": "plain: root -> 16 children -> 1024 FP64 each, whole job host to host",
+                       "payload_bytes": info.payload_bytes, "arena_bytes": plan.arena_bytes},
+            "latency_ms": {"p50": round(1e3 * pct(lat, 50), 4), "p99": round(1e3 * pct(lat, 99), 4)},
+            "note": "launch- and latency-bound; no roofline"}
 
 
 def bench_batched(args, torch, dc):
@@ -396,14 +475,43 @@ def bench_batched(args, torch, dc):
                      "stage_GBps": round(plan.arena_bytes / stage_s / 1e9, 2)}}
 
 
-def bench_served(args, torch, dc, njobs=200, bytes_hi=64 << 20, rho=0.8, budget=200 * 10 ** 9):
+def _served_run(dc, ctx, schema, pool, sizes, jobs, outs, lam, budget):
+    """Submits the jobs at Poisson times of rate lam (jobs/s; 0: all at once)
+    and waits for all; returns the latencies, the stats and the wall time."""
+    import random
+    rng = random.Random(7)
+    srv = dc.Server(ctx, schema, budget_bytes=budget, max_inflight=16, nstreams=4)
+    t0 = time.perf_counter()
+    ids = []
+    next_t = 0.0
+    for si, key, a, b in jobs:
+        if lam > 0:
+            next_t += rng.expovariate(lam)
+            while time.perf_counter() - t0 < next_t:
+                time.sleep(0.0002)
+        o = outs[si]
+        ids.append(srv.submit(pool[si].root_type, pool[si].roots[0], o.ctypes.data, o.nbytes, a, b, key=key))
+    res = [srv.wait(i) for i in ids]
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return [r.t_done - r.t_submit for r in res], st, wall
+
+
+def bench_served(args, torch, dc, budget=200 * 10 ** 9):
     """Served jobs: Poisson arrivals of broom structures (depth U{2..8},
     fan-out U{1..64}, leaf bytes log-uniform 4 KiB..bytes_hi, FP32 or FP64),
-    half of them reusing a resident structure from a pool of 64."""
+    half of them reusing a resident structure from a pool of 64, at offered
+    loads of 0.5, 0.8 and 0.95 of the measured link capacity, then all at
+    once (capacity), then the same jobs one structure per call. Jobs on one
+    structure share one result buffer (results are checked by the tests, not
+    here), written before the clock starts."""
     import random
-    import numpy as np
     import fixtures as fx
+    njobs = 2000 if args.full else 400
+    bytes_hi = (256 << 20) if args.full else (64 << 20)
     rng = random.Random(190601132)
+    fx.set_threads(0)
     pool = [fx.broom(seed=190601132 + i, bytes_lo=4096, bytes_hi=bytes_hi) for i in range(64)]
     schema = dc.Schema(pool[0].types)
     ctx = dc.Context(0)
@@ -416,37 +524,54 @@ def bench_served(args, torch, dc, njobs=200, bytes_hi=64 << 20, rho=0.8, budget=
         si = rng.randrange(64)
         reuse = rng.random() < 0.5
         jobs.append((si, (si + 1) if reuse else 0, rng.choice([1.0001, 0.9999]), rng.choice([0.5, -0.25])))
-    mean_bytes = sum(sizes[si][0] for si, _, _, _ in jobs) / njobs
-    lam = rho * LINK_PEAK_GBPS * 1e9 / mean_bytes  # jobs per second at offered load rho
-    # result buffers, written once before the clock starts so that the copy-out
-    # does not pay first-touch page faults
-    outs = [np.ones(max(sizes[si][1], 1), np.uint8) for si, _, _, _ in jobs]
-    srv = dc.Server(ctx, schema, budget_bytes=budget, max_inflight=16, nstreams=4)
-    t0 = time.perf_counter()
-    ids = []
-    next_t = 0.0
-    for (si, key, a, b), o in zip(jobs, outs):
-        next_t += rng.expovariate(lam)
-        while time.perf_counter() - t0 < next_t:
-            time.sleep(0.0002)
-        ids.append(srv.submit(pool[si].root_type, pool[si].roots[0], o.ctypes.data, o.nbytes, a, b, key=key))
-    res = [srv.wait(i) for i in ids]
-    wall = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
-    lat = [r.t_done - r.t_submit for r in res]
+    outs = [np.ones(max(sz[1], 1), np.uint8) for sz in sizes]
+    peak = link_peak(torch)
+    cap = min(peak["h2d"], peak["d2h"]) * 1e9      # measured link capacity, bytes/s per direction
+    # bytes a job moves over the busier direction: the image back, and the tree in unless it is resident
+    mean_bytes = sum(max(sizes[si][1], 0 if key else sizes[si][0]) for si, key, _, _ in jobs) / njobs
+    loads = {}
+    for rho in (0.5, 0.8, 0.95):
+        lat, st, wall = _served_run(dc, ctx, schema, pool, sizes, jobs, outs, rho * cap / mean_bytes, budget)
+        log(args, f"served rho={rho}: wall {wall:.2f} s, p50 {1e3 * pct(lat, 50):.1f} ms")
+        loads[str(rho)] = {"p50_ms": round(1e3 * pct(lat, 50), 3), "p99_ms": round(1e3 * pct(lat, 99), 3),
+                           "wall_s": round(wall, 3), "h2d_GBps": round(st.h2d_bytes / wall / 1e9, 2),
+                           "d2h_GBps": round(st.d2h_bytes / wall / 1e9, 2), "reused": st.reused,
+                           "evictions": st.evictions, "peak_bytes": st.peak_bytes}
+    lat, st, wall = _served_run(dc, ctx, schema, pool, sizes, jobs, outs, 0, budget)
     moved = st.h2d_bytes + st.d2h_bytes
+    capacity = {"wall_s": round(wall, 3), "jobs_per_s": round(njobs / wall, 1),
+                "h2d_GBps": round(st.h2d_bytes / wall / 1e9, 2), "d2h_GBps": round(st.d2h_bytes / wall / 1e9, 2),
+                "busier_direction_frac_of_measured": round(max(st.h2d_bytes, st.d2h_bytes) / wall / cap, 4),
+                "busier_direction_frac_of_spec": round(max(st.h2d_bytes, st.d2h_bytes) / wall / 1e9 / LINK_PEAK_GBPS, 4)}
+    # the plain path: one structure per call, back to back, no residency
+    plain_lat = []
+    t0 = time.perf_counter()
+    for si, key, a, b in jobs[: min(njobs, 200)]:
+        ta = time.perf_counter()
+        plan = dc.Plan(schema, pool[si].root_type, pool[si].roots)
+        arena = torch.empty(max(plan.arena_bytes, 16), dtype=torch.uint8, device="cuda")
+        scratch = torch.empty(max(plan.scratch_bytes, 16), dtype=torch.uint8, device="cuda")
+        d_out = torch.empty(max(sizes[si][1], 16), dtype=torch.uint8, device="cuda")
+        tree = dc.Tree(ctx, plan, arena, scratch)
+        tree.run_kernel(mode="resolved", select="all", iters=1, a=a, b=b, out=d_out)
+        torch.from_numpy(outs[si][: sizes[si][1]]).copy_(d_out[: sizes[si][1]])
+        plain_lat.append(time.perf_counter() - ta)
+        tree.release()
+        del arena, scratch, d_out
+    plain_wall = time.perf_counter() - t0
+    main = loads["0.8"]
     return {"metric": "deep-copy+kernel effective GB/s vs HBM/link roofline; p50/p99 latency",
             "value": round((moved + st.kernel_bytes) / wall / 1e9, 2), "unit": "GB/s",
-            "config": {"workload": f"served: {njobs} Poisson jobs at offered load {rho} of the link, broom trees "
-                                   f"depth U{{2..8}} fan-out U{{1..64}}, leaf bytes log-uniform 4KiB..{bytes_hi}, "
-                                   f"reuse 0.5 over 64 structures, budget {budget}"},
-            "latency_ms": {"p50": round(1e3 * pct(lat, 50), 3), "p99": round(1e3 * pct(lat, 99), 3)},
-            "link": {"h2d_bytes": st.h2d_bytes, "d2h_bytes": st.d2h_bytes,
-                     "link_GBps": round(moved / wall / 1e9, 2),
-                     "frac_of_spec_one_direction": round(max(st.h2d_bytes, st.d2h_bytes) / wall / 1e9 / LINK_PEAK_GBPS, 4)},
+            "config": {"workload": f"served: {njobs} jobs, broom trees depth U{{2..8}} fan-out U{{1..64}}, leaf bytes "
+                                   f"log-uniform 4KiB..{bytes_hi}, reuse 0.5 over 64 structures, budget {budget}; "
+                                   f"value = all jobs submitted at once (capacity)"},
+            "latency_ms": {"p50": main["p50_ms"], "p99": main["p99_ms"], "at_offered_load": 0.8},
+            "link": {"measured_capacity_GBps": round(cap / 1e9, 2), "spec_GBps": LINK_PEAK_GBPS, **capacity},
+            "offered_load": loads,
+            "plain_path": {"jobs": len(plain_lat), "jobs_per_s": round(len(plain_lat) / plain_wall, 1),
+                           "p50_ms": round(1e3 * pct(plain_lat, 50), 3), "p99_ms": round(1e3 * pct(plain_lat, 99), 3)},
             "server": {"completed": st.completed, "reused": st.reused, "evictions": st.evictions,
-                       "admitted_while_busy": st.batches, "peak_bytes": st.peak_bytes, "wall_s": round(wall, 3)}}
+                       "admitted_while_busy": st.batches, "peak_bytes": st.peak_bytes}}
 
 
 def _time_marshal(torch, dc, ctx, t, chains, allused, reps):
@@ -628,6 +753,8 @@ def main():
         out = bench_copycal(args, torch, dc)
     elif args.workload == "sweep":
         out = bench_sweep(args, torch, dc)
+    elif args.workload == "plain":
+        out = bench_plain(args, torch, dc)
     else:
         out = bench_served(args, torch, dc)
     out.setdefault("n_gpus", 1)

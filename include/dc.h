@@ -338,6 +338,9 @@ dc_status dc_tree_release(dc_tree tree);
 /* Waits for `stream`, then reports a device-side error recorded by earlier
  * passes of this tree (DC_E_STATE) or DC_OK. */
 dc_status dc_tree_check(dc_tree tree, void* stream);
+/* The layout of a deep copy on the device: as dc_plan_objects, except that
+ * `offset` is replaced by the object's device address (d_arena + offset). */
+dc_status dc_tree_objects(dc_tree tree, dc_object* out, uint64_t cap, uint64_t* n);
 
 /* ---- batched form: one persistent launch ------------------------------------------ */
 

@@ -142,9 +142,30 @@ dc_status ctx_wait_ring(dc_ctx ctx) {
   return DC_OK;
 }
 
+// Chunk boundaries of a staged transfer of [lo, hi): sizes double from 1 MiB
+// up to the ring's chunk size and halve again towards the end, so that the
+// first transfer starts after a short pack (upload) and the last scatter is
+// short (download) while the middle runs in full chunks.
+std::vector<uint64_t> chunk_bounds(uint64_t lo, uint64_t hi, uint64_t max_chunk) {
+  std::vector<uint64_t> b{lo};
+  if (max_chunk == 0) max_chunk = 1;
+  const uint64_t small = std::min<uint64_t>(1ull << 20, max_chunk);
+  uint64_t ramp = small, pos = lo;
+  while (pos < hi) {
+    const uint64_t left = hi - pos;
+    uint64_t c = std::min({ramp, max_chunk, std::max(small, (left + 1) / 2)});
+    if (c >= left) c = left;
+    pos += c;
+    b.push_back(pos);
+    ramp = std::min(ramp * 2, max_chunk);  // stays >= 1: the loop always advances
+  }
+  return b;
+}
+
 dc_status upload_source(dc_ctx ctx, uint8_t* dst, uint64_t total, const PieceSource& src, hipStream_t s) {
-  for (uint64_t lo = 0; lo < total; lo += ctx->chunk_bytes) {
-    const uint64_t hi = std::min(total, lo + ctx->chunk_bytes);
+  const std::vector<uint64_t> bounds = chunk_bounds(0, total, ctx->chunk_bytes);
+  for (size_t i = 0; i + 1 < bounds.size(); i++) {
+    const uint64_t lo = bounds[i], hi = bounds[i + 1];
     int k;
     DC_TRY(ring_slot(ctx, &k));
     pack_range(ctx, ctx->ring[k], lo, hi, src);
@@ -170,12 +191,12 @@ dc_status upload_pieces(dc_ctx ctx, uint8_t* dst, uint64_t total, const std::vec
 dc_status download(dc_ctx ctx, const uint8_t* src, uint64_t lo, uint64_t hi, hipStream_t s,
                    const std::function<void(const uint8_t*, uint64_t, uint64_t)>& consume) {
   DC_TRY(ctx_wait_ring(ctx));
-  const uint64_t ch = ctx->chunk_bytes;
-  const uint64_t n = hi > lo ? (hi - lo + ch - 1) / ch : 0;
+  const std::vector<uint64_t> bounds = hi > lo ? chunk_bounds(lo, hi, ctx->chunk_bytes) : std::vector<uint64_t>{lo};
+  const uint64_t n = bounds.size() - 1;
   const int R = dc_ctx_s::kRing;
   auto issue = [&](uint64_t i) -> dc_status {
     const int k = (int)(i % R);
-    const uint64_t a = lo + i * ch, b = std::min(hi, a + ch);
+    const uint64_t a = bounds[i], b = bounds[i + 1];
     DC_HIP(hipMemcpyAsync(ctx->ring[k], src + a, b - a, hipMemcpyDeviceToHost, s));
     DC_HIP(hipEventRecord(ctx->ev[k], s));
     ctx->pending[k] = true;
@@ -186,7 +207,7 @@ dc_status download(dc_ctx ctx, const uint8_t* src, uint64_t lo, uint64_t hi, hip
     const int k = (int)(i % R);
     DC_HIP(hipEventSynchronize(ctx->ev[k]));
     ctx->pending[k] = false;
-    const uint64_t a = lo + i * ch, b = std::min(hi, a + ch);
+    const uint64_t a = bounds[i], b = bounds[i + 1];
     consume(ctx->ring[k], a, b);
     if (i + R < n) DC_TRY(issue(i + R));
   }

@@ -453,6 +453,14 @@ dc_status dc_tree_check(dc_tree t, void* stream) {
   return tree_check(t, (hipStream_t)stream);
 }
 
+dc_status dc_tree_objects(dc_tree t, dc_object* out, uint64_t cap, uint64_t* n) {
+  if (!t || t->released) return fail(DC_E_INVAL, "dc_tree_objects: null or released tree");
+  DC_TRY(dc_plan_objects(t->plan, out, cap, n));
+  const uint64_t m = std::min<uint64_t>(cap, t->plan->objs.size());
+  for (uint64_t i = 0; i < m; i++) out[i].offset += (uint64_t)(uintptr_t)t->arena;
+  return DC_OK;
+}
+
 dc_status dc_tree_release(dc_tree t) {
   if (!t) return fail(DC_E_INVAL, "dc_tree_release: null tree");
   t->released = true;

@@ -135,6 +135,7 @@ _SIGS = {
     "dc_copy_back": [vp, u32, vp],
     "dc_tree_release": [vp],
     "dc_tree_check": [vp, vp],
+    "dc_tree_objects": [vp, ctypes.POINTER(Object), u64, ctypes.POINTER(u64)],
     "dc_batch_run": [vp, ctypes.POINTER(KernelArgs), ctypes.POINTER(Tune), u32, vp],
     "dc_autotune": [vp, ctypes.POINTER(KernelArgs), u32, ctypes.POINTER(Tune)],
     "dc_graph_create": [vp, ctypes.POINTER(KernelArgs), ctypes.POINTER(Tune), u32, ctypes.c_int, ctypes.c_int,
@@ -365,6 +366,14 @@ class Tree:
 
     def check(self, stream=None):
         _check(load().dc_tree_check(self.h, _stream_ptr(stream)), "dc_tree_check")
+
+    def objects(self) -> np.ndarray:
+        """The plan's objects with `off` holding each object's device address."""
+        n = u64()
+        _check(load().dc_tree_objects(self.h, None, 0, ctypes.byref(n)), "dc_tree_objects")
+        arr = (Object * max(1, n.value))()
+        _check(load().dc_tree_objects(self.h, arr, n.value, ctypes.byref(n)), "dc_tree_objects")
+        return np.frombuffer(bytes(arr), OBJECT_DTYPE, count=n.value).copy()
 
     def kick_drift(self, type_id, x_field, v_field, f_field, dt, dt_over_m, steps=1, stream=None):
         """v <- fma(f, dt_over_m, v); x <- fma(v, dt, x) per step on every

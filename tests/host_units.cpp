@@ -1,0 +1,66 @@
+// Host-side units of libdc run on the CPU:
+//  * the thread pool: many short rounds back to back, each with its own work
+//    function, from two callers on two pools at once; every item of every
+//    round must run exactly once with its own round's function;
+//  * the chunk schedule of staged transfers: chunks tile [lo, hi) exactly,
+//    none is empty or larger than the ring's chunk, for sizes from 0 bytes
+//    to 1 TiB (a schedule that doubled past 2^64 once looped forever).
+#include <stdio.h>
+
+#include <atomic>
+#include <thread>
+#include <vector>
+
+#include "dc_host.h"
+
+// defined beside the kernels in the library; the pool does not use it
+namespace dc {
+int device_cu_count() { return 256; }
+}
+
+static int stress(dc::Pool& pool, int rounds, int salt) {
+  int bad = 0;
+  for (int r = 0; r < rounds; r++) {
+    const int n = 2 + (r * 7 + salt) % 15;
+    std::vector<std::atomic<int>> hits(n);
+    for (auto& h : hits) h.store(0);
+    const int tag = r ^ salt;
+    std::atomic<int> wrong{0};
+    pool.run(n, [&, tag](int i) {
+      if (i < 0 || i >= n || tag != (r ^ salt)) wrong++;
+      else hits[i]++;
+    });
+    for (auto& h : hits) bad += h.load() != 1;
+    bad += wrong.load();
+  }
+  return bad;
+}
+
+static int check_bounds() {
+  int bad = 0;
+  const uint64_t sizes[] = {0, 1, 100, (1ull << 20) - 1, 1ull << 20, (1ull << 20) + 1, 5ull << 20, 128ull << 20,
+                            (128ull << 20) + 12345, 958621952ull, 12169061120ull, 1ull << 40};
+  for (uint64_t chunk : {1ull << 20, 16ull << 20, 64ull << 20})
+    for (uint64_t lo : {0ull, 4096ull, 123456789ull})
+      for (uint64_t sz : sizes) {
+        const std::vector<uint64_t> b = dc::chunk_bounds(lo, lo + sz, chunk);
+        if (b.front() != lo || b.back() != lo + sz) bad++;
+        for (size_t i = 0; i + 1 < b.size(); i++)
+          if (b[i + 1] <= b[i] || b[i + 1] - b[i] > chunk) bad++;
+        if (sz >= (64ull << 20) && b.size() > sz / chunk + 32) bad++;  // full chunks in the middle
+      }
+  printf("chunk schedule: %d bad\n", bad);
+  return bad;
+}
+
+int main(int argc, char** argv) {
+  if (check_bounds()) return 2;
+  const int rounds = argc > 1 ? atoi(argv[1]) : 20000;
+  dc::Pool a(8), b(8);
+  int bad_a = 0, bad_b = 0;
+  std::thread t([&] { bad_b = stress(b, rounds, 5); });
+  bad_a = stress(a, rounds, 3);
+  t.join();
+  printf("rounds %d, bad items %d %d\n", rounds, bad_a, bad_b);
+  return bad_a || bad_b;
+}

@@ -247,3 +247,25 @@ def test_errors(ctx):
         tree.check()
     assert e.value.name == "STATE"
     ctypes.memmove(child + 8, old, 8)
+
+
+def test_tree_objects_are_device_addresses(ctx):
+    t = fx.random_tree(7, max_objects=10, nroots=2)
+    c = Copy(ctx, t)
+    objs = c.tree.objects()
+    want = c.oracle.objects()          # offsets relative to the arena start
+    assert len(objs) == len(want)
+    assert np.array_equal(objs["off"].astype(np.uint64), want["off"].astype(np.uint64) + np.uint64(c.base))
+    for name in ("host", "bytes", "count", "kind"):
+        assert np.array_equal(objs[name], want[name]), name
+    # every relocated pointer in the arena names one of these addresses
+    starts = set(int(x) for x in objs["off"])
+    ar = c.device_arena()
+    for o in want:
+        if o["kind"] == 0:
+            ty = t.types[int(o["type"])]
+            for e in range(int(o["count"])):
+                for f in ty.fields:
+                    at = int(o["off"]) + e * ty.size + f.offset
+                    p = int(ar[at:at + 8].view(np.uint64)[0])
+                    assert p == 0 or p in starts
