@@ -257,7 +257,9 @@ def bench_linear(args, torch, dc):
                             "pinned_peak_h2d_GBps": round(peak["h2d"], 2), "pinned_peak_d2h_GBps": round(peak["d2h"], 2),
                             "spec_peak_GBps": LINK_PEAK_GBPS,
                             "h2d_frac_of_spec": round(max(h2d) / LINK_PEAK_GBPS, 4),
-                            "d2h_frac_of_spec": round(max(d2h) / LINK_PEAK_GBPS, 4)}
+                            "d2h_frac_of_spec": round(max(d2h) / LINK_PEAK_GBPS, 4),
+                            "h2d_frac_of_measured": round(max(h2d) / peak["h2d"], 4),
+                            "d2h_frac_of_measured": round(max(d2h) / peak["d2h"], 4)}
         job_bytes = plan.arena_bytes + leaf + 2 * kernel_bytes
         out["end_to_end"] = {"what": "pack + H2D + attach + both kernels + copy back, host buffers in and out",
                              "GBps": round(job_bytes / min(e2e) / 1e9, 2),
