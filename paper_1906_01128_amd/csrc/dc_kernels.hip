@@ -554,8 +554,8 @@ __global__ void __launch_bounds__(256) k_leaf_tiles(Tables t, LeafArgs la, uint6
 // ---- molecular dynamics: kick then drift on sibling leaves ------------------------------
 //
 // One tile: a range of 16-byte chunks of the elements' arrays laid end to
-// end (each element contributes ceil(count / 2) chunks), at most
-// kTileMaxLeaves elements. The element's three array addresses are read once
+// end (each element contributes ceil(count / 2) chunks; 512 per tile), at
+// most kTileMaxLeaves elements. The element's three array addresses are read once
 // per tile from its relocated slots (the resolved form of Section 3) and
 // checked against the arena; per chunk: v = fma(f, dt/m, v), x = fma(v, dt, x).
 constexpr size_t kKdLds = (size_t)(kTileMaxLeaves + 2) * 5 * 8;
@@ -763,7 +763,7 @@ hipError_t launch_scalar(const Tables& t, const DevScalar* refs, const DevScalar
 hipError_t launch_kick_drift(const Tables& t, const KickDriftArgs& k, hipStream_t s) {
   if (k.ntiles == 0) return hipSuccess;
   const uint64_t grid = k.ntiles < (1u << 20) ? k.ntiles : (1u << 20);
-  hipLaunchKernelGGL(k_kick_drift<4>, dim3((uint32_t)grid), dim3(256), 0, s, t, k);
+  hipLaunchKernelGGL(k_kick_drift<2>, dim3((uint32_t)grid), dim3(256), 0, s, t, k);
   return hipGetLastError();
 }
 
