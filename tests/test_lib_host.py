@@ -133,3 +133,38 @@ def test_plan_errors_match_oracle():
     with pytest.raises(dc.DcError) as ed:
         dc.Plan(dc.Schema(types), 0, [p1], align=8)
     assert ed.value.name == "INVAL"
+
+
+# ---- dc_chain_query: the host walk of the pointerchain transfer (no device) ----------------
+
+
+def test_chain_query_matches_oracle_chains():
+    from paper_1906_01128_amd import dc
+    import oracle as orc
+    t = fx.dense(seed=fx.SEED_BASE + 5, q=3, n=17, D=3, packed_last=0)
+    schema = dc.Schema(t.types)
+    ref = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 0)
+    for lv in range(4):
+        for idx in range(3):
+            chain = [(1, idx)] * lv + [(0, 0)]
+            q = dc.chain_query(schema, t.root_type, t.roots[0], chain)
+            _, count, kind = ref.resolve_chain(0, chain)
+            assert (q.count, dc.KIND_NAME[q.kind], q.dev_addr) == (count, kind, 0)
+
+
+def test_chain_query_errors():
+    from paper_1906_01128_amd import dc
+    t = fx.linear(seed=fx.SEED_BASE + 6, k=3, n=10, scheme=1)
+    schema = dc.Schema(t.types)
+    for bad in ([(0, 0)],                      # level 0 has no data array
+                [(1, 1), (1, 0), (0, 0)],      # index past the one-element next array
+                [(1, 0), (0, 0), (0, 0)],      # a step through a primitive array
+                [(2, 0)],                      # no such field
+                []):                           # empty chain
+        with pytest.raises(dc.DcError):
+            dc.chain_query(schema, 0, t.roots[0], bad)
+    q = dc.chain_query(schema, 0, t.roots[0], [(1, 0), (1, 0), (0, 0)])
+    assert q.count == 10 and dc.KIND_NAME[q.kind] == "f64"
+    # a chain that ends in a struct array is described (the transfer itself refuses it)
+    q = dc.chain_query(schema, 0, t.roots[0], [(1, 0)])
+    assert dc.KIND_NAME[q.kind] == "struct" and q.count == 1
