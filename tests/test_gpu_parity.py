@@ -138,6 +138,16 @@ def test_wide_all_leaves(ctx):
     assert_same_bytes(c.device_arena(), c.oracle.arena(), "wide arena after kernel")
 
 
+@pytest.mark.slow
+def test_wide_1g_all_leaves(ctx):
+    """The wide-1G variant (leaf lengths up to 2^18, ~0.96 GB), whole arena."""
+    t = fx.wide(hi=1 << 18)
+    c = Copy(ctx, t)
+    c.tree.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.5)
+    c.oracle.run_kernel(1.0001, 0.5, iters=1, select="all")
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "wide-1G arena after kernel")
+
+
 def test_wide_deref_each_small(ctx):
     t = fx.wide(f1=6, f2=5, lo=1, hi=300)
     c = Copy(ctx, t)

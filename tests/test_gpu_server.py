@@ -97,3 +97,59 @@ def test_budget_admission_and_eviction(ctx):
         assert e.value.name == "BUDGET"
     small.close()
     srv.close()
+
+
+@pytest.mark.slow
+def test_served_full_size_sampled(ctx):
+    """The served workload's full distribution (leaf bytes up to 256 MiB, fan-out
+    up to 64, depth up to 8): 12 jobs on 6 structures, the second job on each
+    reusing the resident copy, all in flight together under the 200 GB budget. Each output leaf is
+    checked on 2048 sampled elements against the oracle's fma, element by
+    element, and its size against the plan."""
+    from paper_1906_01128_amd import dc
+    fx.set_threads(0)
+    structs = [fx.broom(seed=190601132 + i, bytes_lo=4096, bytes_hi=256 << 20) for i in range(6)]
+    schema = dc.Schema(structs[0].types)
+    rng = random.Random(5)
+    # every job names its structure's key: the second job on a structure finds it resident
+    jobs = [(i % 6, i % 6 + 1, rng.randrange(4)) for i in range(12)]
+    srv = dc.Server(ctx, schema, budget_bytes=200 * 10 ** 9, max_inflight=16, nstreams=4)
+    outs, ids = [], []
+    for si, key, ab in jobs:
+        t = structs[si]
+        plan = dc.Plan(schema, t.root_type, t.roots)
+        buf = np.empty(max(plan.info().out_bytes, 1), np.uint8)
+        outs.append((buf, plan.objects()))
+        ids.append(srv.submit(t.root_type, t.roots[0], buf.ctypes.data, buf.nbytes, *AB[ab], key=key))
+    res = [srv.wait(i, timeout=600.0) for i in ids]
+    st = srv.stats()
+    srv.close()
+    assert all(r.status == 0 for r in res)
+    assert st.reused == 6
+    srng = np.random.default_rng(9)
+    for (buf, objs), (si, _, ab), r in zip(outs, jobs, res):
+        a, b = AB[ab]
+        af, bf = float(np.float32(a)), float(np.float32(b))
+        # the leaf image: FP32/FP64 leaves in arena order, each at the next
+        # 64-byte boundary after the previous one's end
+        pos = 0
+        first = True
+        for o in objs:
+            if o["kind"] not in (1, 2) or o["count"] == 0:
+                continue
+            off = 0 if first else (pos + 63) // 64 * 64
+            first = False
+            n, es = int(o["count"]), (8 if o["kind"] == 2 else 4)
+            pos = off + n * es
+            src = np.ctypeslib.as_array((ctypes.c_uint8 * (n * es)).from_address(int(o["host"])))
+            idx = srng.integers(0, n, size=min(n, 2048))
+            if o["kind"] == 2:
+                x = src.view(np.float64)[idx]
+                got = buf[off:off + n * 8].view(np.float64)[idx]
+                want = np.array([orc.fma64(float(v), a, b) for v in x])
+            else:
+                x = src.view(np.float32)[idx]
+                got = buf[off:off + n * 4].view(np.float32)[idx]
+                want = np.array([orc.fma32(float(v), af, bf) for v in x], np.float32)
+            assert np.array_equal(got.view(np.uint8), want.view(np.uint8)), f"job on structure {si}"
+        assert pos <= buf.nbytes
