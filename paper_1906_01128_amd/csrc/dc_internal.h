@@ -207,6 +207,7 @@ struct Tables {  // device addresses of the scratch tables
   uint8_t* arena;
   uint64_t arena_bytes;
   uint64_t nseg, nleaves, total_chunks;
+  uint32_t ntypes, pad;
 };
 
 hipError_t launch_relocate(const Tables& t, bool attach, hipStream_t s);

@@ -28,9 +28,24 @@ __device__ __forceinline__ u32x4 gload16(uint64_t a) { return *(const g_u32x4*)a
 __device__ __forceinline__ void gstore16(uint64_t a, u32x4 v) { *(g_u32x4*)a = v; }
 
 
-// LDS of one relocation unit: open-addressing hash of (key -> object) and
-// the slot prefix of the struct arrays the unit spans.
-constexpr size_t kRelocLds = kSegHashSlots * 8 + kSegHashSlots * 4 + (kSegMaxSObjs + 1) * 8;
+// What relocation needs of a struct type (the full DevType is 528 bytes).
+struct RelocType {
+  uint32_t size, nptr, follow, pad;
+  uint32_t ptr_off[kMaxFields];
+};
+
+// LDS of one relocation unit: an open-addressing hash from a slot's current
+// value to its translated value, and the struct arrays the unit spans (their
+// slot prefix and placement) and the types, so that a slot costs one global
+// load (its value) and one store.
+struct RelocLds {
+  uint64_t keys[kSegHashSlots];
+  uint64_t vals[kSegHashSlots];
+  uint64_t pre[kSegMaxSObjs + 1];
+  DevSObj sobj[kSegMaxSObjs];
+  RelocType types[kMaxTypes];
+};
+constexpr size_t kRelocLds = sizeof(RelocLds);
 
 __device__ __forceinline__ uint32_t hash_slot(uint64_t key) {
   // multiplicative hashing; keys are 16-byte aligned addresses
@@ -38,7 +53,7 @@ __device__ __forceinline__ uint32_t hash_slot(uint64_t key) {
 }
 static_assert(kSegHashSlots == 1024, "hash_slot assumes 2^10 slots");
 
-__device__ __forceinline__ void hash_insert(uint64_t* keys, uint32_t* vals, uint64_t key, uint32_t val) {
+__device__ __forceinline__ void hash_insert(uint64_t* keys, uint64_t* vals, uint64_t key, uint64_t val) {
   uint32_t h = hash_slot(key);
   for (uint32_t probe = 0; probe < kSegHashSlots; probe++) {
     unsigned long long prev = atomicCAS((unsigned long long*)&keys[h], 0ull, (unsigned long long)key);
@@ -50,15 +65,19 @@ __device__ __forceinline__ void hash_insert(uint64_t* keys, uint32_t* vals, uint
   }
 }
 
-__device__ __forceinline__ uint32_t hash_find(const uint64_t* keys, const uint32_t* vals, uint64_t key) {
+// the translated value of key, or false if key is not one of the unit's targets
+__device__ __forceinline__ bool hash_find(const uint64_t* keys, const uint64_t* vals, uint64_t key, uint64_t* val) {
   uint32_t h = hash_slot(key);
   for (uint32_t probe = 0; probe < kSegHashSlots; probe++) {
     uint64_t k = keys[h];
-    if (k == key) return vals[h];
-    if (k == 0) return kNone;
+    if (k == key) {
+      *val = vals[h];
+      return true;
+    }
+    if (k == 0) return false;
     h = (h + 1) & (kSegHashSlots - 1);
   }
-  return kNone;
+  return false;
 }
 
 __device__ __forceinline__ void report_bad_slot(DevHeader* hdr, uint64_t slot_off) {
@@ -85,22 +104,30 @@ __device__ __noinline__ void report_wild(DevHeader* hdr) {
 // value that is not one of the unit's planned targets is left alone and
 // reported in the header.
 __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t* lds) {
-  uint64_t* keys = (uint64_t*)lds;
-  uint32_t* vals = (uint32_t*)(keys + kSegHashSlots);
-  uint64_t* pre = (uint64_t*)(vals + kSegHashSlots);
+  RelocLds* L = (RelocLds*)lds;
   const int tid = threadIdx.x, bs = blockDim.x;
   const DevSeg seg = t.segs[sg];
   const uint64_t B = (uint64_t)t.arena;
 
-  for (uint32_t i = tid; i < kSegHashSlots; i += bs) keys[i] = 0;
+  // stage: the unit's struct arrays and slot prefix, the types, and the
+  // translation of every target (host address <-> arena address)
+  for (uint32_t i = tid; i < kSegHashSlots; i += bs) L->keys[i] = 0;
   const uint32_t nso = seg.sobj_hi - seg.sobj_lo;
-  for (uint32_t i = tid; i <= nso; i += bs) pre[i] = t.sobj_pre[seg.sobj_lo + i];
+  for (uint32_t i = tid; i <= nso; i += bs) L->pre[i] = t.sobj_pre[seg.sobj_lo + i];
+  for (uint32_t i = tid; i < nso; i += bs) L->sobj[i] = t.sobj[seg.sobj_lo + i];
+  for (uint32_t i = tid; i < t.ntypes; i += bs) {
+    const DevType* ty = &t.types[i];
+    L->types[i].size = ty->size;
+    L->types[i].nptr = ty->nptr;
+    L->types[i].follow = ty->follow;
+    for (uint32_t f = 0; f < kMaxFields; f++) L->types[i].ptr_off[f] = ty->ptr_off[f];
+  }
   __syncthreads();
   const uint32_t ntgt = (uint32_t)(seg.tgt_hi - seg.tgt_lo);
   for (uint32_t i = tid; i < ntgt; i += bs) {
-    uint32_t obj = t.targets[seg.tgt_lo + i];
-    uint64_t key = attach ? t.obj_host[obj] : B + t.obj_off[obj];
-    hash_insert(keys, vals, key, obj);
+    const uint32_t obj = t.targets[seg.tgt_lo + i];
+    const uint64_t host = t.obj_host[obj], dev = B + t.obj_off[obj];
+    hash_insert(L->keys, L->vals, attach ? host : dev, attach ? dev : host);
   }
   __syncthreads();
 
@@ -117,19 +144,18 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
       uint32_t lo = 0, hi = nso;
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (pre[mid] <= j) lo = mid;
+        if (L->pre[mid] <= j) lo = mid;
         else hi = mid;
       }
-      const DevSObj so = t.sobj[seg.sobj_lo + lo];
-      const DevType* ty = &t.types[so.type];
-      const uint32_t nptr = ty->nptr;
-      const uint64_t local = j - pre[lo];
-      const uint64_t e = local / nptr;
-      const uint32_t f = (uint32_t)(local - e * nptr);
-      soff[k] = so.off + e * ty->size + ty->ptr_off[f];
+      const DevSObj so = L->sobj[lo];
+      const RelocType& ty = L->types[so.type];
+      const uint64_t local = j - L->pre[lo];
+      const uint64_t e = local / ty.nptr;
+      const uint32_t f = (uint32_t)(local - e * ty.nptr);
+      soff[k] = so.off + e * ty.size + ty.ptr_off[f];
       val[k] = *(const g_u64*)(B + soff[k]);
       // a member left out of a selective copy reads as null on the device
-      if (!((ty->follow >> f) & 1u)) {
+      if (!((ty.follow >> f) & 1u)) {
         if (val[k] != 0) *(g_u64*)(B + soff[k]) = 0;
         val[k] = 0;
       }
@@ -137,12 +163,12 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       if (soff[k] == ~0ull || val[k] == 0) continue;
-      const uint32_t obj = hash_find(keys, vals, val[k]);
-      if (obj == kNone) {
+      uint64_t nv;
+      if (!hash_find(L->keys, L->vals, val[k], &nv)) {
         report_bad_slot(t.hdr, soff[k]);
         continue;
       }
-      *(g_u64*)(B + soff[k]) = attach ? B + t.obj_off[obj] : t.obj_host[obj];
+      *(g_u64*)(B + soff[k]) = nv;
     }
   }
 }

@@ -31,6 +31,7 @@ static Tables make_tables(dc_plan p, uint8_t* arena, uint8_t* scratch) {
   t.nseg = p->segs.size();
   t.nleaves = p->leaves.size();
   t.total_chunks = p->total_chunks;
+  t.ntypes = (uint32_t)p->dev_types.size();
   return t;
 }
 
