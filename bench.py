@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E
-LINK_PEAK_GBPS = 63.0       # PCIe Gen5 x16 per direction after encoding (32 GT/s x16 on the box)
+LINK_PEAK_GBPS = 63.0       # PCIe Gen5 x16 per direction after encoding (32 GT/s x16)
 
 
 def traffic(workload, kernel):
@@ -736,7 +736,7 @@ def bench_copycal(args, torch, dc):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}). "
               f"Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
