@@ -145,7 +145,7 @@ dc_status dc_chain_copy_back(dc_ctx ctx, dc_schema schema, uint32_t root_type, c
                     const int nparts = (int)((hi - lo + part - 1) / part);
                     pool->run(nparts, [&](int k) {
                       const uint64_t a = lo + (uint64_t)k * part, b = std::min(hi, a + part);
-                      memcpy(host + a, buf + (a - lo), b - a);
+                      copy_stream(host + a, buf + (a - lo), b - a);
                     });
                   }));
   return DC_OK;

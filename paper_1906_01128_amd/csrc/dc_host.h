@@ -104,6 +104,8 @@ struct PieceSource {
   std::function<uint64_t(uint64_t)> first_ending_after;  // first piece with off + bytes > x
 };
 dc_status upload_source(dc_ctx ctx, uint8_t* dst, uint64_t total, const PieceSource& src, hipStream_t s);
+// memcpy for bulk data: non-temporal stores above 4 KiB (see dc_host.cpp)
+void copy_stream(void* dst, const void* src, uint64_t n);
 // Chunk boundaries of a staged transfer of [lo, hi): 1 MiB first, doubling up
 // to max_chunk, halving again over the last chunks.
 std::vector<uint64_t> chunk_bounds(uint64_t lo, uint64_t hi, uint64_t max_chunk);

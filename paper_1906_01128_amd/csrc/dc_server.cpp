@@ -376,7 +376,7 @@ void dc_server_s::done_loop() {
           const uint64_t a = std::max(plo, p->leaf_out[l]);
           const uint64_t b =
               std::min<uint64_t>(phi, p->leaf_out[l] + (p->leaf_info[l] & ((1ull << kLeafKindShift) - 1)));
-          if (b > a) memcpy(out + a, buf + (a - lo), b - a);
+          if (b > a) copy_stream(out + a, buf + (a - lo), b - a);
         }
       });
     });

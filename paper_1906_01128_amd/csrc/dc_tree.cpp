@@ -426,7 +426,7 @@ dc_status dc_copy_back(dc_tree t, uint32_t flags, void* stream) {
           if (b <= a) continue;
           uint8_t* host = (uint8_t*)(uintptr_t)o.host;
           if (o.kind != DC_KIND_STRUCT) {
-            if (leaves) memcpy(host + (a - o.off), buf + (a - clo), b - a);
+            if (leaves) copy_stream(host + (a - o.off), buf + (a - clo), b - a);
           } else if (scalars) {
             const TypeDesc& ty = p->types[o.type];
             for (uint64_t x = a; x < b;) {

@@ -2,11 +2,13 @@
 //  * the thread pool: many short rounds back to back, each with its own work
 //    function, from two callers on two pools at once; every item of every
 //    round must run exactly once with its own round's function;
+//  * the non-temporal bulk copy: every size and alignment, no byte outside;
 //  * the chunk schedule of staged transfers: chunks tile [lo, hi) exactly,
 //    none is empty or larger than the ring's chunk, for sizes from 0 bytes
 //    to 1 TiB (a schedule that doubled past 2^64 once looped forever).
 #include <stdio.h>
 
+#include <algorithm>
 #include <atomic>
 #include <thread>
 #include <vector>
@@ -53,8 +55,28 @@ static int check_bounds() {
   return bad;
 }
 
+static int check_copy() {
+  // non-temporal bulk copy: every size and alignment lands byte for byte
+  int bad = 0;
+  std::vector<uint8_t> src((2 << 20) + 256), dst((2 << 20) + 256);
+  for (size_t i = 0; i < src.size(); i++) src[i] = (uint8_t)(i * 131 + 7);
+  const uint64_t sizes[] = {0, 1, 15, 4095, 4096, 4097, 4096 + 63, 65536 + 5, (1u << 20) + 17, 2u << 20};
+  for (uint64_t n : sizes)
+    for (int so : {0, 1, 8, 15})
+      for (int dof : {0, 3, 8, 16, 33}) {
+        std::fill(dst.begin(), dst.end(), 0xEE);
+        dc::copy_stream(dst.data() + dof, src.data() + so, n);
+        for (uint64_t i = 0; i < n; i++) bad += dst[dof + i] != src[so + i];
+        bad += dof > 0 && dst[dof - 1] != 0xEE;
+        bad += dst[dof + n] != 0xEE;
+      }
+  printf("bulk copy: %d bad\n", bad);
+  return bad;
+}
+
 int main(int argc, char** argv) {
   if (check_bounds()) return 2;
+  if (check_copy()) return 3;
   const int rounds = argc > 1 ? atoi(argv[1]) : 20000;
   dc::Pool a(8), b(8);
   int bad_a = 0, bad_b = 0;
