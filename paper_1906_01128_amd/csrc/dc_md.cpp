@@ -95,7 +95,8 @@ static dc_status kd_prepare(dc_tree t, const dc_kick_drift_args* a, hipStream_t 
   std::vector<DevTile> tiles;
   DC_TRY(kd_build(t, a, tri, pre, tiles));
   if (kd) {
-    DC_HIP(hipStreamSynchronize(s));
+    // earlier launches on any stream may still read the old list
+    DC_HIP(hipDeviceSynchronize());
     if (kd->buf) DC_HIP(hipFree(kd->buf));
     delete kd;
     kd = nullptr;
