@@ -154,6 +154,8 @@ dc_status tree_ensure_tiles(dc_tree t, uint32_t T, hipStream_t s) {
   }
   if (T < kTileMinChunks || T > kTileMaxChunks || (T & (T - 1))) return fail(DC_E_INVAL, "tile of %u chunks", T);
   if (t->plan->leaves.empty()) return DC_OK;
+  // the list is rewritten in place: kernels on other streams may still read the old one
+  if (t->tile_T != 0) DC_HIP(hipDeviceSynchronize());
   if (!t->tiles_ev) DC_HIP(hipEventCreateWithFlags(&t->tiles_ev, hipEventDisableTiming));
   const std::vector<DevTile> tiles = build_tiles(t->plan, T);
   const uint64_t bytes = sizeof(DevTile) * tiles.size();
@@ -190,7 +192,7 @@ static dc_status ensure_paths(dc_tree t, hipStream_t s) {
   DC_TRY(upload_pieces(t->ctx, t->scratch + p->sl.paths, sizeof(DevPath) * paths.size(), pcs, s));
   std::vector<Piece> hp{{0, hops.data(), 8 * hops.size()}};
   DC_TRY(upload_pieces(t->ctx, t->scratch + p->sl.hops, 8 * hops.size(), hp, s));
-  DC_TRY(ctx_wait_ring(t->ctx));
+  DC_TRY(ctx_wait_ring(t->ctx));  // complete before any stream uses them
   t->paths_uploaded = true;
   return DC_OK;
 }
