@@ -280,9 +280,13 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     p->obj_off[i] = p->objs[i].off;
   }
 
-  // relocation units over the slot enumeration
+  // relocation units over the slot enumeration. A small tree is cut into
+  // smaller units so that its relocation spreads over more workgroups (it is
+  // latency-bound); a large one uses full units.
   {
     const uint64_t nslots = w.nslots;
+    uint64_t unit_slots = 128;
+    while (unit_slots < kSegMaxSlots && nslots / unit_slots > 256) unit_slots *= 2;
     std::vector<uint32_t> mark(nobj, kNone);
     uint32_t seg_id = 0, ntgt = 0;
     DevSeg cur{};
@@ -311,7 +315,7 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
       for (uint64_t j = p->sobj_pre[so]; j < p->sobj_pre[so + 1]; j++) {
         const uint32_t t = p->slot_target[j];
         const bool new_tgt = t != kNone && mark[t] != seg_id;
-        if (j - cur.slot_lo >= kSegMaxSlots || (new_tgt && ntgt == kSegMaxTargets)) {
+        if (j - cur.slot_lo >= unit_slots || (new_tgt && ntgt == kSegMaxTargets)) {
           close(j, so + 1);
           cur = DevSeg{};
           cur.slot_lo = j;
