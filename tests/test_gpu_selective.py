@@ -174,3 +174,27 @@ def test_linear_allinit_allused_both_schemes(ctx):
             got = np.ctypeslib.as_array((ctypes.c_uint8 * int(o["bytes"])).from_address(int(o["host"])))
             want = c.oracle.arena()[int(o["off"]): int(o["off"]) + int(o["bytes"])]
             assert np.array_equal(got, want)
+
+
+def test_selective_batched_and_graph(ctx):
+    """A selective plan through the batched form: relocation zeroes the
+    unfollowed members and the leaf pass covers only the copied arrays."""
+    t = fx.md(seed=12, nsims=40, cells_lo=2, cells_hi=30, mean_atoms=7)
+    follow = [(1 << len(ty.fields)) - 1 for ty in t.types]
+    follow[-1] = 0b101  # positions and forces, not velocities
+    for tune in (dict(tile_chunks=1024, launches=1), dict(block=256, wg_per_cu=4, tile_chunks=1024)):
+        c = Copy(ctx, t, relocate=False, follow=follow)
+        c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=False, tune=tune)
+        c.oracle.run_kernel(1.0001, 0.5, iters=1, select="all")
+        assert_same_bytes(c.device_arena(), c.oracle.arena(), f"selective batched {tune}")
+        c.tree.check()
+
+
+def test_scalar_chain_through_unfollowed_member_is_refused(ctx):
+    from paper_1906_01128_amd import dc
+    t = fx.random_tree(0, max_objects=10)    # its root's next member is not null on the host
+    c = Copy(ctx, t, follow=[0b101, 0b11])   # but it is not followed: null in the copy
+    temps = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(dc.DcError):
+        c.tree.scalar_declare([(0, [(1, 0)], 32, 8)], temps)
+    c.tree.scalar_declare([(0, [], 32, 8)], temps)   # the root's own tag is fine
