@@ -13,7 +13,14 @@
  *     one batch, then attach every pointer on the device);
  *   - resolving a pointer chain once to its effective address (Section 3);
  *   - running the kernel once and transferring the tree back (Algorithm 2,
- *     steps 4 and 5; the scaling kernel of Sections 4.1.2 and 4.2.2).
+ *     steps 4 and 5; the scaling kernel of Sections 4.1.2 and 4.2.2);
+ *   - the selective deep copy (Section 2), the pointerchain transfer scheme
+ *     that moves only the array a chain ends in, and scalar chains with
+ *     write-back (Section 3), and a molecular-dynamics leaf kernel on the
+ *     atoms-in-cells structure of Section 3's example;
+ *   - a batched form (every structure of a plan relocated and computed per
+ *     launch, captured in a HIP graph, autotuned) and a served form
+ *     (admission under a device-memory budget, resident structures).
  *
  * Conventions for every call:
  *   - Returns dc_status: DC_OK (0) or a negative DC_E_* code. The text of the
@@ -212,16 +219,19 @@ dc_status dc_resolve_chain(dc_tree tree, uint64_t root_index, const dc_step* ste
 /* The pointerchain transfer scheme (Section 3): resolve a chain on the host
  * tree and transfer only the array it ends in; the structures along the
  * chain are not copied, since the kernel needs only the effective address.
- * dc_chain_to_device walks the chain from the host struct `root` (type
- * root_type) and copies the final array (count * element size bytes) into
- * d_buf (a 16-byte aligned device buffer of buf_bytes); *out receives d_buf,
- * the count and the kind. Returns once the host array has been read.
+ *
+ * dc_chain_query: the count and kind of the host array a chain ends in
+ * (out->dev_addr = 0), so that the caller can size d_buf. Needs no device.
  * Errors: DC_E_INVAL (bad field or steps), DC_E_RANGE (null before the end,
- * index past an array, buffer too small). */
-/* The count and kind of the host array a chain ends in (out->dev_addr = 0),
- * so that the caller can size d_buf. Needs no device. Errors as below. */
+ * index past an array). */
 dc_status dc_chain_query(dc_schema schema, uint32_t root_type, const void* root, const dc_step* steps,
                          uint32_t nsteps, dc_chain* out);
+/* dc_chain_to_device walks the chain from the host struct `root` (type
+ * root_type) and copies the final FP32/FP64 array (count * element size
+ * bytes) into d_buf (a 16-byte aligned device buffer of buf_bytes); *out
+ * receives d_buf, the count and the kind. Returns once the host array has
+ * been read. Errors: as dc_chain_query, DC_E_RANGE for a buffer too small
+ * or misaligned, DC_E_INVAL for a chain that ends in a struct array. */
 dc_status dc_chain_to_device(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* root, const dc_step* steps,
                              uint32_t nsteps, void* d_buf, uint64_t buf_bytes, void* stream, dc_chain* out);
 /* `iters` passes of x = fma(x, a, b) (FP64: a, b; FP32: af, bf) over an array
@@ -342,10 +352,10 @@ dc_status dc_tree_check(dc_tree tree, void* stream);
  * `offset` is replaced by the object's device address (d_arena + offset). */
 dc_status dc_tree_objects(dc_tree tree, dc_object* out, uint64_t cap, uint64_t* n);
 
-/* ---- batched form: one persistent launch ------------------------------------------ */
+/* ---- batched form ------------------------------------------------------------------ */
 
-/* Tile shapes of the persistent relocate+compute kernel. Zero fields take
- * the tuned or default choice. */
+/* Launch shape of the batched relocate+compute work. Zero fields (other than
+ * launches) take the tuned or default choice. */
 typedef struct {
   uint32_t block;          /* threads per workgroup: 256, 512 or 1024 */
   uint32_t wg_per_cu;      /* resident workgroups per compute unit */
@@ -384,8 +394,9 @@ dc_status dc_graph_destroy(dc_graph graph);
 /* ---- served form ---------------------------------------------------------------- */
 
 /* A server admits deep-copy+kernel jobs against a device-memory budget,
- * keeps copied structures resident for reuse, overlaps the transfers and
- * kernels of several jobs, and batches the kernels of ready jobs. */
+ * keeps copied structures resident for reuse, and admits new jobs while
+ * others are on the device (continuous batching), overlapping their
+ * transfers and kernels on several streams. */
 typedef struct {
   uint64_t budget_bytes;   /* device bytes for arenas, scratch and outputs */
   uint32_t max_inflight;   /* jobs on the device at once */
