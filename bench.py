@@ -377,6 +377,56 @@ def bench_plain(args, torch, dc, reps=1000):
             "note": "launch- and latency-bound; no roofline"}
 
 
+def _batched_vs_plain(torch, dc, ctx, t, tune, nsub):
+    """The first nsub simulations two ways, device-resident and staged: one
+    plan over all of them run as the batched form (one graph replay), and one
+    plan per simulation, each with its own attach, leaf pass and detach."""
+    schema = dc.Schema(t.types)
+    s = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    plan = dc.Plan(schema, t.root_type, t.roots[:nsub])
+    arena = torch.empty(plan.arena_bytes, dtype=torch.uint8, device="cuda")
+    scratch = torch.empty(plan.scratch_bytes, dtype=torch.uint8, device="cuda")
+    tree = dc.Tree(ctx, plan, arena, scratch, relocate=False)
+    g = tree.graph(a=1.0001, b=0.5, tune=tune)
+    g.launch()
+    e0, e1 = ev(), ev()
+    e0.record(s)
+    for _ in range(5):
+        g.launch()
+    e1.record(s)
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1) / 5
+    leaf = plan.info().leaf_bytes
+    g.close()
+    tree.release()
+    del arena, scratch
+    trees = []
+    for r in t.roots[:nsub]:
+        p = dc.Plan(schema, t.root_type, [r])
+        a = torch.empty(p.arena_bytes, dtype=torch.uint8, device="cuda")
+        sc = torch.empty(p.scratch_bytes, dtype=torch.uint8, device="cuda")
+        trees.append((p, a, sc, dc.Tree(ctx, p, a, sc, relocate=False)))
+    for _, _, _, tr in trees:   # warm: tile lists built
+        tr.attach()
+        tr.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.5)
+        tr.detach()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _, _, _, tr in trees:
+        tr.attach()
+        tr.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.5)
+        tr.detach()
+    e1.record(s)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    for _, _, _, tr in trees:
+        tr.release()
+    return {"simulations": nsub, "batched_ms": round(batched_ms, 3), "per_structure_ms": round(plain_ms, 3),
+            "batched_GBps": round(2 * leaf / batched_ms / 1e6, 1), "per_structure_GBps": round(2 * leaf / plain_ms / 1e6, 1),
+            "speedup": round(plain_ms / batched_ms, 2)}
+
+
 def bench_batched(args, torch, dc):
     """The batched MD workload: 10,000 simulations, ~7.8 M arrays, ~12 GB.
     Step = one replay of the captured graph that attaches every pointer,
@@ -447,6 +497,7 @@ def bench_batched(args, torch, dc):
     tree.detach()
     kd_bytes = 40 * (info.leaf_bytes // 24)    # per double of x: read x, v, f; write x, v
     kd_gbps = kd_bytes / pct(kd, 50) / 1e9
+    plain = _batched_vs_plain(torch, dc, ctx, t, tune, nsub=500)
     kb = 2 * info.leaf_bytes
     rb = 2 * (info.nslots_nonnull * 16 + info.nslots * 8 + info.nobjects * 16)
     v = (kb + rb) / pct(step_s, 50) / 1e9
@@ -470,6 +521,7 @@ def bench_batched(args, torch, dc):
                          "avg_launch_us": round(1e6 * k_s, 1)},
             "latency_ms": {"p50": round(1e3 * pct(step_s, 50), 3), "p99": round(1e3 * pct(step_s, 99), 3)},
             "separate_launches_ms": {k: round(pct(v_, 50), 3) for k, v_ in phases.items()},
+            "one_structure_per_call": plain,
             "kick_drift": {"kernel": "k_kick_drift", "ms": round(1e3 * pct(kd, 50), 3),
                            "bytes_per_launch": kd_bytes, "achieved_GBps": round(kd_gbps, 1),
                            "frac": round(kd_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic("batched", "k_kick_drift")},
