@@ -815,7 +815,7 @@ def main():
     out.setdefault("data", "synthetic")
     if not args.no_cpu_baseline and args.workload == "linear":
         log(args, "cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline_linear(args, passes=args.passes)
+        out["cpu_baseline"] = cpu_baseline_linear(args, passes=2 * args.passes)   # ~10-15 s of CPU work
     print(json.dumps(out), flush=True)
 
 
