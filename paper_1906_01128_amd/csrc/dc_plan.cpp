@@ -1,7 +1,7 @@
-// libdc planner: the host walk that sizes and lays out the tree
-// (Algorithm 1's "determine the total bytes", with space handed out in the
-// order the walk requests it), the relocation work units, the leaf tables and
-// the scratch layout the kernels read.
+// libdc planner: the host walk that sizes and lays out the tree (the sizing
+// step of Algorithm 1, with space handed out in the order the walk requests
+// it), the relocation work units, the leaf tables and the scratch layout the
+// kernels read.
 #include <string.h>
 
 #include <algorithm>
