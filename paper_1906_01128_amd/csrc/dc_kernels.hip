@@ -27,6 +27,17 @@ typedef __attribute__((address_space(1))) uint64_t g_u64;
 __device__ __forceinline__ u32x4 gload16(uint64_t a) { return *(const g_u32x4*)a; }
 __device__ __forceinline__ void gstore16(uint64_t a, u32x4 v) { *(g_u32x4*)a = v; }
 
+// Workgroup barrier that orders LDS accesses only. __syncthreads() also
+// orders global memory, which on CDNA means waiting until every store of the
+// wave has completed (one counter covers loads and stores): a loop that
+// reuses LDS between rounds of streamed stores would pay a write round trip
+// per round.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 
 // What relocation needs of a struct type (the full DevType is 528 bytes).
 struct RelocType {
@@ -36,16 +47,23 @@ struct RelocType {
 
 // LDS of one relocation unit: an open-addressing hash from a slot's current
 // value to its translated value, and the struct arrays the unit spans (their
-// slot prefix and placement) and the types, so that a slot costs one global
-// load (its value) and one store.
+// placement, and their slot prefix relative to the unit's first slot), then
+// the types of the plan, so that a slot costs one global load (its value) and
+// one store. About 19.5 KB plus 80 bytes per type: eight workgroups of a
+// plan with up to a dozen types fit one CU's 160 KB.
 struct RelocLds {
   uint64_t keys[kSegHashSlots];
   uint64_t vals[kSegHashSlots];
-  uint64_t pre[kSegMaxSObjs + 1];
-  DevSObj sobj[kSegMaxSObjs];
-  RelocType types[kMaxTypes];
+  uint64_t sobj[kSegMaxSObjs];     // arena offset | type << 56
+  uint32_t rel[kSegMaxSObjs + 4];  // slot prefix - first slot, clamped to [0, slots of the unit]
+  // RelocType types[ntypes] follows
 };
-constexpr size_t kRelocLds = sizeof(RelocLds);
+constexpr int kSObjTypeShift = 56;
+static_assert(sizeof(RelocLds) % 16 == 0, "types start 16-byte aligned");
+
+__host__ __device__ constexpr size_t reloc_lds_bytes(uint32_t ntypes) {
+  return sizeof(RelocLds) + (size_t)ntypes * sizeof(RelocType);
+}
 
 __device__ __forceinline__ uint32_t hash_slot(uint64_t key) {
   // multiplicative hashing; keys are 16-byte aligned addresses
@@ -105,54 +123,65 @@ __device__ __noinline__ void report_wild(DevHeader* hdr) {
 // reported in the header.
 __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t* lds) {
   RelocLds* L = (RelocLds*)lds;
+  RelocType* types = (RelocType*)(lds + sizeof(RelocLds));
   const int tid = threadIdx.x, bs = blockDim.x;
   const DevSeg seg = t.segs[sg];
   const uint64_t B = (uint64_t)t.arena;
+  const uint64_t nslots = seg.slot_hi - seg.slot_lo;
+  // slot prefix of the unit's first struct array, which may begin before the unit
+  const uint64_t pre0 = t.sobj_pre[seg.sobj_lo];
 
   // stage: the unit's struct arrays and slot prefix, the types, and the
   // translation of every target (host address <-> arena address)
   for (uint32_t i = tid; i < kSegHashSlots; i += bs) L->keys[i] = 0;
   const uint32_t nso = seg.sobj_hi - seg.sobj_lo;
-  for (uint32_t i = tid; i <= nso; i += bs) L->pre[i] = t.sobj_pre[seg.sobj_lo + i];
-  for (uint32_t i = tid; i < nso; i += bs) L->sobj[i] = t.sobj[seg.sobj_lo + i];
+  for (uint32_t i = tid; i <= nso; i += bs) {
+    const uint64_t pr = t.sobj_pre[seg.sobj_lo + i];
+    const uint64_t c = pr < seg.slot_lo ? seg.slot_lo : (pr > seg.slot_hi ? seg.slot_hi : pr);
+    L->rel[i] = (uint32_t)(c - seg.slot_lo);
+  }
+  for (uint32_t i = tid; i < nso; i += bs) {
+    const DevSObj so = t.sobj[seg.sobj_lo + i];
+    L->sobj[i] = so.off | (uint64_t)so.type << kSObjTypeShift;
+  }
   for (uint32_t i = tid; i < t.ntypes; i += bs) {
     const DevType* ty = &t.types[i];
-    L->types[i].size = ty->size;
-    L->types[i].nptr = ty->nptr;
-    L->types[i].follow = ty->follow;
-    for (uint32_t f = 0; f < kMaxFields; f++) L->types[i].ptr_off[f] = ty->ptr_off[f];
+    types[i].size = ty->size;
+    types[i].nptr = ty->nptr;
+    types[i].follow = ty->follow;
+    for (uint32_t f = 0; f < kMaxFields; f++) types[i].ptr_off[f] = ty->ptr_off[f];
   }
-  __syncthreads();
+  lds_barrier();
   const uint32_t ntgt = (uint32_t)(seg.tgt_hi - seg.tgt_lo);
   for (uint32_t i = tid; i < ntgt; i += bs) {
     const uint32_t obj = t.targets[seg.tgt_lo + i];
     const uint64_t host = t.obj_host[obj], dev = B + t.obj_off[obj];
     hash_insert(L->keys, L->vals, attach ? host : dev, attach ? dev : host);
   }
-  __syncthreads();
+  lds_barrier();
 
   // four slots per thread per round, their loads issued together
-  for (uint64_t jb = seg.slot_lo; jb < seg.slot_hi; jb += 4 * (uint64_t)bs) {
+  for (uint64_t jb = 0; jb < nslots; jb += 4 * (uint64_t)bs) {
     uint64_t soff[4], val[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      const uint64_t j = jb + (uint64_t)k * bs + tid;
+      const uint32_t jr = (uint32_t)(jb + (uint64_t)k * bs + tid);  // slot - first slot
       soff[k] = ~0ull;
       val[k] = 0;
-      if (j >= seg.slot_hi) continue;
-      // struct array holding slot j: largest i with pre[i] <= j
+      if (jr >= nslots) continue;
+      // struct array holding the slot: largest i with rel[i] <= jr
       uint32_t lo = 0, hi = nso;
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (L->pre[mid] <= j) lo = mid;
+        if (L->rel[mid] <= jr) lo = mid;
         else hi = mid;
       }
-      const DevSObj so = L->sobj[lo];
-      const RelocType& ty = L->types[so.type];
-      const uint64_t local = j - L->pre[lo];
+      const uint64_t so = L->sobj[lo];
+      const RelocType& ty = types[so >> kSObjTypeShift];
+      const uint64_t local = lo == 0 ? seg.slot_lo + jr - pre0 : (uint64_t)(jr - L->rel[lo]);
       const uint64_t e = local / ty.nptr;
       const uint32_t f = (uint32_t)(local - e * ty.nptr);
-      soff[k] = so.off + e * ty.size + ty.ptr_off[f];
+      soff[k] = (so & ((1ull << kSObjTypeShift) - 1)) + e * ty.size + ty.ptr_off[f];
       val[k] = *(const g_u64*)(B + soff[k]);
       // a member left out of a selective copy reads as null on the device
       if (!((ty.follow >> f) & 1u)) {
@@ -173,11 +202,11 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
   }
 }
 
-__global__ void __launch_bounds__(kRelocBlock) k_relocate(Tables t, int attach) {
-  __shared__ __align__(16) uint8_t lds[kRelocLds];
+__global__ void __launch_bounds__(kRelocBlock, 8) k_relocate(Tables t, int attach) {
+  extern __shared__ __align__(16) uint8_t lds[];
   for (uint64_t sg = blockIdx.x; sg < t.nseg; sg += gridDim.x) {
     relocate_unit(t, sg, attach != 0, lds);
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -708,8 +737,11 @@ __device__ __forceinline__ void report_done(uint32_t* ctr, uint32_t n, bool rele
   }
 }
 
-template <int U>
-__global__ void k_batch(Tables t, LeafArgs la, uint32_t flags, uint64_t ntiles, uint32_t per_item) {
+// BS threads per workgroup; resources held to eight waves per SIMD, so that
+// a CU runs 2048 threads of the loop at once, as it does for the leaf kernel
+template <int U, int BS>
+__global__ void __launch_bounds__(BS, 8) k_batch(Tables t, LeafArgs la, uint32_t flags, uint64_t ntiles,
+                                                  uint32_t per_item) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ uint32_t s_item;
   DevHeader* hdr = t.hdr;
@@ -721,9 +753,9 @@ __global__ void k_batch(Tables t, LeafArgs la, uint32_t flags, uint64_t ntiles, 
   bool pastA = false, pastB = false, waitedB = false;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(&hdr->queue, 1u);
-    __syncthreads();
+    lds_barrier();
     const uint32_t item = s_item;
-    __syncthreads();
+    lds_barrier();
     if (!pastA && item >= nA) {
       report_done(&hdr->doneA, myA, true);
       pastA = true;
@@ -736,7 +768,7 @@ __global__ void k_batch(Tables t, LeafArgs la, uint32_t flags, uint64_t ntiles, 
     if (item >= total) break;
     if (item < nA) {
       relocate_unit(t, item, true, lds);
-      __syncthreads();
+      lds_barrier();
       myA++;
     } else if (item < nA + nB) {
       if (myB == 0) wait_count(hdr, &hdr->doneA, nA);
@@ -750,7 +782,7 @@ __global__ void k_batch(Tables t, LeafArgs la, uint32_t flags, uint64_t ntiles, 
         waitedB = true;
       }
       relocate_unit(t, item - nA - nB, false, lds);
-      __syncthreads();
+      lds_barrier();
     }
   }
 }
@@ -775,7 +807,9 @@ int device_cu_count() {
 hipError_t launch_relocate(const Tables& t, bool attach, hipStream_t s) {
   if (t.nseg == 0) return hipSuccess;
   const uint64_t grid = t.nseg < 65536 ? t.nseg : 65536;
-  hipLaunchKernelGGL(k_relocate, dim3((uint32_t)grid), dim3(kRelocBlock), 0, s, t, attach ? 1 : 0);
+  if (t.ntypes > kMaxTypes) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_relocate, dim3((uint32_t)grid), dim3(kRelocBlock), reloc_lds_bytes(t.ntypes), s, t,
+                     attach ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -789,7 +823,13 @@ hipError_t launch_scalar(const Tables& t, const DevScalar* refs, const DevScalar
 hipError_t launch_kick_drift(const Tables& t, const KickDriftArgs& k, hipStream_t s) {
   if (k.ntiles == 0) return hipSuccess;
   const uint64_t grid = k.ntiles < (1u << 20) ? k.ntiles : (1u << 20);
-  hipLaunchKernelGGL(k_kick_drift<2>, dim3((uint32_t)grid), dim3(256), 0, s, t, k);
+  // LDS reserved beyond the kernel's own so that at most five workgroups
+  // share a CU (160 KB of LDS each): five array streams per thread at full
+  // occupancy oversubscribe HBM. Measured on 10,000 MD simulations (19.8 GB
+  // per step): 4.07 ms at five workgroups per CU, 4.47 ms at eight.
+  constexpr size_t kPerWg = 160 * 1024 / 5 - 2048;
+  static_assert(kPerWg > 160 * 1024 / 6 && kPerWg > kKdLds, "five workgroups per CU");
+  hipLaunchKernelGGL(k_kick_drift<2>, dim3((uint32_t)grid), dim3(256), kPerWg - kKdLds, s, t, k);
   return hipGetLastError();
 }
 
@@ -853,21 +893,24 @@ hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint64_t ntile
 
 hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
                         uint64_t ntiles, hipStream_t s) {
-  size_t lds = kTileLds > kRelocLds ? kTileLds : kRelocLds;
+  if (t.ntypes > kMaxTypes) return hipErrorInvalidValue;
+  const size_t rl = reloc_lds_bytes(t.ntypes);
+  const size_t lds = kTileLds > rl ? kTileLds : rl;
   // compute tiles are taken a few at a time, so that the queue sees about 32
   // items per workgroup rather than one atomic per tile
   const uint64_t per = ntiles / ((uint64_t)grid * 32 + 1) + 1;
   const uint32_t per_item = (uint32_t)(per > 256 ? 256 : per);
-  // chunks per thread per round: 1024 chunks per workgroup round
+  // chunks per thread per round: two rounds of 1024 chunks per workgroup in
+  // flight (512 with 256 threads, where four chunks a round would spill)
   switch (block) {
     case 256:
-      hipLaunchKernelGGL(k_batch<4>, dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
+      hipLaunchKernelGGL((k_batch<2, 256>), dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
       break;
     case 512:
-      hipLaunchKernelGGL(k_batch<2>, dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
+      hipLaunchKernelGGL((k_batch<2, 512>), dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
       break;
     case 1024:
-      hipLaunchKernelGGL(k_batch<1>, dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
+      hipLaunchKernelGGL((k_batch<1, 1024>), dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
       break;
     default:
       return hipErrorInvalidValue;

@@ -272,6 +272,9 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     p->payload_bytes += o.bytes;
   }
   p->arena_bytes = nobj ? align_up(end, align) : 0;
+  // the relocation kernel packs an arena offset and a type into 64 bits
+  if (p->arena_bytes >= (1ull << 48))
+    return fail(DC_E_RANGE, "arena of %llu bytes (limit 2^48)", (unsigned long long)p->arena_bytes);
   for (DevSObj& so : p->sobj) so.off = p->objs[so.obj].off;
   p->obj_host.resize(nobj);
   p->obj_off.resize(nobj);
