@@ -279,3 +279,65 @@ def test_tree_objects_are_device_addresses(ctx):
                     at = int(o["off"]) + e * ty.size + f.offset
                     p = int(ar[at:at + 8].view(np.uint64)[0])
                     assert p == 0 or p in starts
+
+
+def _many_types_tree(seed=5):
+    """64 struct types (the schema's limit) in a chain: T_i holds a pointer to
+    an array of T_{i+1} (two elements every 16 levels, else one) and an FP64
+    leaf; the last type has 16 pointer members (the most a type may have),
+    each to an FP64 leaf."""
+    n = 64
+    types = []
+    for i in range(n - 1):
+        types.append(fx.Type(f"T{i}", 8 * (2 + i % 4), 8,
+                             [fx.Field(0, "struct", i + 1, fixed_count=2 if i % 16 == 0 else 1),
+                              fx.Field(8, "f64", fixed_count=3 + i % 7)]))
+    types.append(fx.Type(f"T{n - 1}", 128, 8, [fx.Field(8 * j, "f64", fixed_count=1 + j) for j in range(16)]))
+    t = fx.Tree()
+    t.types = types
+    t.root_type = 0
+    rng = np.random.default_rng(seed)
+
+    def leaf(cnt):
+        buf = (ctypes.c_double * cnt)(*rng.uniform(-1, 1, cnt))
+        t._keep.append(buf)
+        return ctypes.addressof(buf)
+
+    def array(i, cnt):
+        ty = types[i]
+        buf = ctypes.create_string_buffer(ty.size * cnt)
+        t._keep.append(buf)
+        base = ctypes.addressof(buf)
+        for e in range(cnt):
+            for f in ty.fields:
+                p = array(f.type, f.fixed_count) if f.kind == "struct" else leaf(f.fixed_count)
+                ctypes.c_uint64.from_address(base + e * ty.size + f.offset).value = p
+        return base
+
+    t.roots = [array(0, 1)]
+    return t
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_many_types_relocate(ctx, persistent):
+    """Relocation with the largest type table the schema allows (the
+    relocation kernel stages the plan's types in LDS), by the relocation
+    kernel and by the persistent batch kernel."""
+    t = _many_types_tree()
+    c = Copy(ctx, t, relocate=False)
+    assert len(t.types) == 64
+    assert_same_bytes(c.device_arena(), c.raw_image(), "staged image")
+    if persistent:
+        c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=False,
+                         tune=dict(block=256, wg_per_cu=2, tile_chunks=1024))
+        c.oracle.run_kernel(1.0001, 0.5, select="all")
+    else:
+        c.tree.attach()
+        assert_same_bytes(c.device_arena(), c.oracle.arena(), "after attach")
+        c.tree.run_kernel(select="all", a=1.0001, b=0.5)
+        c.oracle.run_kernel(1.0001, 0.5, select="all")
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "after kernel")
+    c.tree.detach()
+    c.tree.attach()
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "after detach + attach")
+    c.tree.check()
