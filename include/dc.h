@@ -127,8 +127,10 @@ typedef struct {
 
 /* ---- lifecycle --------------------------------------------------------------- */
 
-/* A context on HIP device `device`: owns pinned host staging buffers and a
- * pool of host threads for packing. */
+/* A context on HIP device `device`: owns pinned host staging buffers (eight
+ * of 32 MiB, 256 MiB in all, allocated here and freed by dc_ctx_destroy) and
+ * a pool of host threads for packing. Errors: DC_E_NOMEM if the pinned
+ * staging cannot be allocated, DC_E_HIP. */
 dc_status dc_ctx_create(int device, dc_ctx* out);
 dc_status dc_ctx_destroy(dc_ctx ctx);
 

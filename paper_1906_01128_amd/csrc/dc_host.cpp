@@ -177,18 +177,20 @@ dc_status ctx_wait_ring(dc_ctx ctx) {
   return DC_OK;
 }
 
-// Chunk boundaries of a staged transfer of [lo, hi): sizes double from 1 MiB
-// up to the ring's chunk size and halve again towards the end, so that the
-// first transfer starts after a short pack (upload) and the last scatter is
-// short (download) while the middle runs in full chunks.
-std::vector<uint64_t> chunk_bounds(uint64_t lo, uint64_t hi, uint64_t max_chunk) {
+// Chunk boundaries of a staged transfer of [lo, hi). ramp_up: sizes double
+// from 1 MiB up to the ring's chunk size, so that the first transfer starts
+// after a short pack (upload). ramp_down: sizes halve over the last chunks,
+// so that the last scatter is short (download). Each copy costs about 10 us
+// of DMA setup on top of its bytes, so the ramps are only where they pay.
+std::vector<uint64_t> chunk_bounds(uint64_t lo, uint64_t hi, uint64_t max_chunk, bool ramp_up, bool ramp_down) {
   std::vector<uint64_t> b{lo};
   if (max_chunk == 0) max_chunk = 1;
   const uint64_t small = std::min<uint64_t>(1ull << 20, max_chunk);
-  uint64_t ramp = small, pos = lo;
+  uint64_t ramp = ramp_up ? small : max_chunk, pos = lo;
   while (pos < hi) {
     const uint64_t left = hi - pos;
-    uint64_t c = std::min({ramp, max_chunk, std::max(small, (left + 1) / 2)});
+    const uint64_t tail = ramp_down ? std::max(small, (left + 1) / 2) : left;
+    uint64_t c = std::min({ramp, max_chunk, tail});
     if (c >= left) c = left;
     pos += c;
     b.push_back(pos);
@@ -198,7 +200,7 @@ std::vector<uint64_t> chunk_bounds(uint64_t lo, uint64_t hi, uint64_t max_chunk)
 }
 
 dc_status upload_source(dc_ctx ctx, uint8_t* dst, uint64_t total, const PieceSource& src, hipStream_t s) {
-  const std::vector<uint64_t> bounds = chunk_bounds(0, total, ctx->chunk_bytes);
+  const std::vector<uint64_t> bounds = chunk_bounds(0, total, ctx->chunk_bytes, true, false);
   for (size_t i = 0; i + 1 < bounds.size(); i++) {
     const uint64_t lo = bounds[i], hi = bounds[i + 1];
     int k;
@@ -226,7 +228,8 @@ dc_status upload_pieces(dc_ctx ctx, uint8_t* dst, uint64_t total, const std::vec
 dc_status download(dc_ctx ctx, const uint8_t* src, uint64_t lo, uint64_t hi, hipStream_t s,
                    const std::function<void(const uint8_t*, uint64_t, uint64_t)>& consume) {
   DC_TRY(ctx_wait_ring(ctx));
-  const std::vector<uint64_t> bounds = hi > lo ? chunk_bounds(lo, hi, ctx->chunk_bytes) : std::vector<uint64_t>{lo};
+  const std::vector<uint64_t> bounds =
+      hi > lo ? chunk_bounds(lo, hi, ctx->chunk_bytes, false, true) : std::vector<uint64_t>{lo};
   const uint64_t n = bounds.size() - 1;
   const int R = dc_ctx_s::kRing;
   auto issue = [&](uint64_t i) -> dc_status {

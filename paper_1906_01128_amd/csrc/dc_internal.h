@@ -62,9 +62,14 @@ struct DevSObj {  // one struct array placed in the arena
   uint32_t obj;
 };
 
+// One target of a relocation unit: the object's host address and arena offset.
+struct DevTarget {
+  uint64_t host, off;
+};
+
 struct DevSeg {
   uint64_t slot_lo, slot_hi;  // slot range [lo, hi)
-  uint64_t tgt_lo, tgt_hi;    // range in the target list
+  uint64_t tgt_lo, tgt_hi;    // range in the target table
   uint32_t sobj_lo, sobj_hi;  // struct objects overlapping the slot range
   uint32_t pad[2];
 };
@@ -115,7 +120,7 @@ enum DevErr : uint32_t {
 };
 
 struct ScratchLayout {
-  uint64_t header, types, obj_host, obj_off, sobj, sobj_pre, segs, targets;
+  uint64_t header, types, sobj, sobj_pre, segs, tgts;
   uint64_t leaf_slot, leaf_pre, leaf_info, leaf_out;
   uint64_t tiles, paths, hops;
   uint64_t static_end;  // [0, static_end) is uploaded with every deep copy
@@ -191,12 +196,10 @@ struct KickDriftArgs {
 struct Tables {  // device addresses of the scratch tables
   DevHeader* hdr;
   const DevType* types;
-  const uint64_t* obj_host;
-  const uint64_t* obj_off;
   const DevSObj* sobj;
   const uint64_t* sobj_pre;  // nsobj + 1 entries (slot prefix)
   const DevSeg* segs;
-  const uint32_t* targets;
+  const DevTarget* tgts;  // every unit's targets, unit after unit
   const uint64_t* leaf_slot;
   const uint64_t* leaf_pre;  // nleaves + 1 entries (16-byte chunk prefix)
   const uint64_t* leaf_info;

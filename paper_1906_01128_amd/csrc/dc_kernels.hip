@@ -120,7 +120,12 @@ __device__ __noinline__ void report_wild(DevHeader* hdr) {
 // Translates every pointer slot of relocation unit `sg`. attach: host address
 // -> arena address; detach: arena address -> host address. A slot holding a
 // value that is not one of the unit's planned targets is left alone and
-// reported in the header.
+// reported in the header. Three dependent rounds of global accesses: the
+// unit's tables; the slots' current values together with the targets'
+// translations; the translated stores. Needs at least 256 threads: a unit's
+// at most 1024 slots are four per thread.
+static_assert(kSegMaxSlots <= 4 * 256, "four slots per thread of a 256-thread workgroup");
+
 __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t* lds) {
   RelocLds* L = (RelocLds*)lds;
   RelocType* types = (RelocType*)(lds + sizeof(RelocLds));
@@ -131,8 +136,7 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
   // slot prefix of the unit's first struct array, which may begin before the unit
   const uint64_t pre0 = t.sobj_pre[seg.sobj_lo];
 
-  // stage: the unit's struct arrays and slot prefix, the types, and the
-  // translation of every target (host address <-> arena address)
+  // stage: the unit's struct arrays and slot prefix, and the types
   for (uint32_t i = tid; i < kSegHashSlots; i += bs) L->keys[i] = 0;
   const uint32_t nso = seg.sobj_hi - seg.sobj_lo;
   for (uint32_t i = tid; i <= nso; i += bs) {
@@ -152,53 +156,56 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
     for (uint32_t f = 0; f < kMaxFields; f++) types[i].ptr_off[f] = ty->ptr_off[f];
   }
   lds_barrier();
+
+  // the thread's slots (at most four): their arena offsets and current values
+  uint64_t soff[4], val[4];
+  bool fol[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const uint32_t jr = (uint32_t)k * bs + tid;  // slot - first slot
+    soff[k] = ~0ull;
+    val[k] = 0;
+    fol[k] = true;
+    if (jr >= nslots) continue;
+    // struct array holding the slot: largest i with rel[i] <= jr
+    uint32_t lo = 0, hi = nso;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (L->rel[mid] <= jr) lo = mid;
+      else hi = mid;
+    }
+    const uint64_t so = L->sobj[lo];
+    const RelocType& ty = types[so >> kSObjTypeShift];
+    const uint64_t local = lo == 0 ? seg.slot_lo + jr - pre0 : (uint64_t)(jr - L->rel[lo]);
+    const uint64_t e = local / ty.nptr;
+    const uint32_t f = (uint32_t)(local - e * ty.nptr);
+    soff[k] = (so & ((1ull << kSObjTypeShift) - 1)) + e * ty.size + ty.ptr_off[f];
+    fol[k] = (ty.follow >> f) & 1u;
+    val[k] = *(const g_u64*)(B + soff[k]);
+  }
+  // the translation of every target (host address <-> arena address), loaded
+  // while the slot values are in flight
   const uint32_t ntgt = (uint32_t)(seg.tgt_hi - seg.tgt_lo);
   for (uint32_t i = tid; i < ntgt; i += bs) {
-    const uint32_t obj = t.targets[seg.tgt_lo + i];
-    const uint64_t host = t.obj_host[obj], dev = B + t.obj_off[obj];
-    hash_insert(L->keys, L->vals, attach ? host : dev, attach ? dev : host);
+    const DevTarget tg = t.tgts[seg.tgt_lo + i];
+    hash_insert(L->keys, L->vals, attach ? tg.host : B + tg.off, attach ? B + tg.off : tg.host);
   }
   lds_barrier();
 
-  // four slots per thread per round, their loads issued together
-  for (uint64_t jb = 0; jb < nslots; jb += 4 * (uint64_t)bs) {
-    uint64_t soff[4], val[4];
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-      const uint32_t jr = (uint32_t)(jb + (uint64_t)k * bs + tid);  // slot - first slot
-      soff[k] = ~0ull;
-      val[k] = 0;
-      if (jr >= nslots) continue;
-      // struct array holding the slot: largest i with rel[i] <= jr
-      uint32_t lo = 0, hi = nso;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (L->rel[mid] <= jr) lo = mid;
-        else hi = mid;
-      }
-      const uint64_t so = L->sobj[lo];
-      const RelocType& ty = types[so >> kSObjTypeShift];
-      const uint64_t local = lo == 0 ? seg.slot_lo + jr - pre0 : (uint64_t)(jr - L->rel[lo]);
-      const uint64_t e = local / ty.nptr;
-      const uint32_t f = (uint32_t)(local - e * ty.nptr);
-      soff[k] = (so & ((1ull << kSObjTypeShift) - 1)) + e * ty.size + ty.ptr_off[f];
-      val[k] = *(const g_u64*)(B + soff[k]);
-      // a member left out of a selective copy reads as null on the device
-      if (!((ty.follow >> f) & 1u)) {
-        if (val[k] != 0) *(g_u64*)(B + soff[k]) = 0;
-        val[k] = 0;
-      }
+  for (int k = 0; k < 4; k++) {
+    if (soff[k] == ~0ull || val[k] == 0) continue;
+    // a member left out of a selective copy reads as null on the device
+    if (!fol[k]) {
+      *(g_u64*)(B + soff[k]) = 0;
+      continue;
     }
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      if (soff[k] == ~0ull || val[k] == 0) continue;
-      uint64_t nv;
-      if (!hash_find(L->keys, L->vals, val[k], &nv)) {
-        report_bad_slot(t.hdr, soff[k]);
-        continue;
-      }
-      *(g_u64*)(B + soff[k]) = nv;
+    uint64_t nv;
+    if (!hash_find(L->keys, L->vals, val[k], &nv)) {
+      report_bad_slot(t.hdr, soff[k]);
+      continue;
     }
+    *(g_u64*)(B + soff[k]) = nv;
   }
 }
 
@@ -900,8 +907,9 @@ hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uin
   // items per workgroup rather than one atomic per tile
   const uint64_t per = ntiles / ((uint64_t)grid * 32 + 1) + 1;
   const uint32_t per_item = (uint32_t)(per > 256 ? 256 : per);
-  // chunks per thread per round: two rounds of 1024 chunks per workgroup in
-  // flight (512 with 256 threads, where four chunks a round would spill)
+  // chunks per thread per round: 1024 chunks per workgroup round (512 with
+  // 256 threads: four chunks per thread would spill within the register
+  // budget of eight waves per SIMD)
   switch (block) {
     case 256:
       hipLaunchKernelGGL((k_batch<2, 256>), dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);

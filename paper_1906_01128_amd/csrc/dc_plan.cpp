@@ -276,12 +276,6 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
   if (p->arena_bytes >= (1ull << 48))
     return fail(DC_E_RANGE, "arena of %llu bytes (limit 2^48)", (unsigned long long)p->arena_bytes);
   for (DevSObj& so : p->sobj) so.off = p->objs[so.obj].off;
-  p->obj_host.resize(nobj);
-  p->obj_off.resize(nobj);
-  for (uint64_t i = 0; i < nobj; i++) {
-    p->obj_host[i] = p->objs[i].host;
-    p->obj_off[i] = p->objs[i].off;
-  }
 
   // relocation units over the slot enumeration. A small tree is cut into
   // smaller units so that its relocation spreads over more workgroups (it is
@@ -296,7 +290,7 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     uint32_t so = 0;
     auto close = [&](uint64_t hi, uint32_t so_hi) {
       cur.slot_hi = hi;
-      cur.tgt_hi = p->targets.size();
+      cur.tgt_hi = p->tgts.size();
       cur.sobj_hi = so_hi;
       if (cur.slot_hi > cur.slot_lo) {
         p->segs.push_back(cur);
@@ -311,7 +305,7 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
         close(p->sobj_pre[so], so);
         cur = DevSeg{};
         cur.slot_lo = p->sobj_pre[so];
-        cur.tgt_lo = p->targets.size();
+        cur.tgt_lo = p->tgts.size();
         cur.sobj_lo = so;
         ntgt = 0;
       }
@@ -322,13 +316,13 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
           close(j, so + 1);
           cur = DevSeg{};
           cur.slot_lo = j;
-          cur.tgt_lo = p->targets.size();
+          cur.tgt_lo = p->tgts.size();
           cur.sobj_lo = so;
           ntgt = 0;
         }
         if (t != kNone && mark[t] != seg_id) {
           mark[t] = seg_id;
-          p->targets.push_back(t);
+          p->tgts.push_back(DevTarget{p->objs[t].host, p->objs[t].off});
           ntgt++;
         }
       }
@@ -394,12 +388,10 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     const uint64_t nl = p->leaves.size();
     s.header = take(sizeof(DevHeader));
     s.types = take(sizeof(DevType) * p->dev_types.size());
-    s.obj_host = take(8 * nobj);
-    s.obj_off = take(8 * nobj);
     s.sobj = take(sizeof(DevSObj) * p->sobj.size());
     s.sobj_pre = take(8 * p->sobj_pre.size());
     s.segs = take(sizeof(DevSeg) * p->segs.size());
-    s.targets = take(4 * p->targets.size());
+    s.tgts = take(sizeof(DevTarget) * p->tgts.size());
     s.leaf_slot = take(8 * nl);
     s.leaf_pre = take(8 * (nl + 1));
     s.leaf_info = take(8 * nl);

@@ -13,12 +13,10 @@ static Tables make_tables(dc_plan p, uint8_t* arena, uint8_t* scratch) {
   Tables t{};
   t.hdr = (DevHeader*)(scratch + s.header);
   t.types = (const DevType*)(scratch + s.types);
-  t.obj_host = (const uint64_t*)(scratch + s.obj_host);
-  t.obj_off = (const uint64_t*)(scratch + s.obj_off);
   t.sobj = (const DevSObj*)(scratch + s.sobj);
   t.sobj_pre = (const uint64_t*)(scratch + s.sobj_pre);
   t.segs = (const DevSeg*)(scratch + s.segs);
-  t.targets = (const uint32_t*)(scratch + s.targets);
+  t.tgts = (const DevTarget*)(scratch + s.tgts);
   t.leaf_slot = (const uint64_t*)(scratch + s.leaf_slot);
   t.leaf_pre = (const uint64_t*)(scratch + s.leaf_pre);
   t.leaf_info = (const uint64_t*)(scratch + s.leaf_info);
@@ -69,12 +67,10 @@ static dc_status upload_tables(dc_ctx ctx, dc_plan p, uint8_t* arena, uint8_t* s
   };
   add(sl.header, &h, sizeof(h));
   add(sl.types, p->dev_types.data(), sizeof(DevType) * p->dev_types.size());
-  add(sl.obj_host, p->obj_host.data(), 8 * p->obj_host.size());
-  add(sl.obj_off, p->obj_off.data(), 8 * p->obj_off.size());
   add(sl.sobj, p->sobj.data(), sizeof(DevSObj) * p->sobj.size());
   add(sl.sobj_pre, p->sobj_pre.data(), 8 * p->sobj_pre.size());
   add(sl.segs, p->segs.data(), sizeof(DevSeg) * p->segs.size());
-  add(sl.targets, p->targets.data(), 4 * p->targets.size());
+  add(sl.tgts, p->tgts.data(), sizeof(DevTarget) * p->tgts.size());
   add(sl.leaf_slot, p->leaf_slot.data(), 8 * p->leaf_slot.size());
   add(sl.leaf_pre, p->leaf_pre.data(), 8 * p->leaf_pre.size());
   add(sl.leaf_info, p->leaf_info.data(), 8 * p->leaf_info.size());

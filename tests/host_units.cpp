@@ -3,9 +3,10 @@
 //    function, from two callers on two pools at once; every item of every
 //    round must run exactly once with its own round's function;
 //  * the non-temporal bulk copy: every size and alignment, no byte outside;
-//  * the chunk schedule of staged transfers: chunks tile [lo, hi) exactly,
-//    none is empty or larger than the ring's chunk, for sizes from 0 bytes
-//    to 1 TiB (a schedule that doubled past 2^64 once looped forever).
+//  * the chunk schedule of staged transfers, with and without the ramps at
+//    either end: chunks tile [lo, hi) exactly, none is empty or larger than
+//    the ring's chunk, for sizes from 0 bytes to 1 TiB (a schedule that
+//    doubled past 2^64 once looped forever).
 #include <stdio.h>
 
 #include <algorithm>
@@ -42,15 +43,21 @@ static int check_bounds() {
   int bad = 0;
   const uint64_t sizes[] = {0, 1, 100, (1ull << 20) - 1, 1ull << 20, (1ull << 20) + 1, 5ull << 20, 128ull << 20,
                             (128ull << 20) + 12345, 958621952ull, 12169061120ull, 1ull << 40};
-  for (uint64_t chunk : {1ull << 20, 16ull << 20, 64ull << 20})
-    for (uint64_t lo : {0ull, 4096ull, 123456789ull})
-      for (uint64_t sz : sizes) {
-        const std::vector<uint64_t> b = dc::chunk_bounds(lo, lo + sz, chunk);
-        if (b.front() != lo || b.back() != lo + sz) bad++;
-        for (size_t i = 0; i + 1 < b.size(); i++)
-          if (b[i + 1] <= b[i] || b[i + 1] - b[i] > chunk) bad++;
-        if (sz >= (64ull << 20) && b.size() > sz / chunk + 32) bad++;  // full chunks in the middle
-      }
+  for (int ramps = 0; ramps < 4; ramps++)
+    for (uint64_t chunk : {1ull << 20, 16ull << 20, 64ull << 20})
+      for (uint64_t lo : {0ull, 4096ull, 123456789ull})
+        for (uint64_t sz : sizes) {
+          const bool up = ramps & 1, down = ramps & 2;
+          const std::vector<uint64_t> b = dc::chunk_bounds(lo, lo + sz, chunk, up, down);
+          if (b.front() != lo || b.back() != lo + sz) bad++;
+          for (size_t i = 0; i + 1 < b.size(); i++)
+            if (b[i + 1] <= b[i] || b[i + 1] - b[i] > chunk) bad++;
+          if (sz >= (64ull << 20) && b.size() > sz / chunk + 32) bad++;  // full chunks in the middle
+          // without a ramp at an end, the chunk there is full (the last one
+          // may be the rest)
+          if (sz >= 4 * chunk && !up && b[1] - b[0] != chunk) bad++;
+          if (sz >= 4 * chunk && !down && b[b.size() - 2] - b[b.size() - 3] != chunk) bad++;
+        }
   printf("chunk schedule: %d bad\n", bad);
   return bad;
 }
