@@ -361,7 +361,8 @@ dc_status dc_tree_objects(dc_tree tree, dc_object* out, uint64_t cap, uint64_t* 
 typedef struct {
   uint32_t block;          /* threads per workgroup: 256, 512 or 1024 */
   uint32_t wg_per_cu;      /* resident workgroups per compute unit */
-  uint32_t tile_chunks;    /* 16-byte chunks per compute tile */
+  uint32_t tile_chunks;    /* 16-byte chunks per compute tile: a power of two,
+                              512..2^20 (DC_E_INVAL otherwise) */
   uint32_t launches;       /* 0: one persistent launch; 1: three ordinary launches
                               (relocate, every leaf, reverse relocate), for which
                               block and wg_per_cu are not used */

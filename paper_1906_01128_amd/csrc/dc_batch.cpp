@@ -125,7 +125,7 @@ static dc_status enqueue_batch(dc_tree t, const LeafArgs& la, const dc_tune& tu,
   if (tu.launches == 1) {
     // the same work as three ordinary launches: relocate, every leaf, reverse
     if (flags & DC_BATCH_ATTACH) e = launch_relocate(t->tab, true, s);
-    if (e == hipSuccess) e = launch_leaf_tiles(t->tab, la, ntiles, false, s);
+    if (e == hipSuccess) e = launch_leaf_tiles(t->tab, la, ntiles, t->tile_T, false, s);
     if (e == hipSuccess && (flags & DC_BATCH_DETACH)) e = launch_relocate(t->tab, false, s);
   } else {
     e = launch_reset_counters(t->tab.hdr, s);
@@ -190,7 +190,7 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
         dc_tune c{block, wg, tile, 0};
         if (check_tune(c) == DC_OK) cands.push_back(c);
       }
-  for (uint32_t tile : {1024u, 2048u, 4096u}) cands.push_back(dc_tune{256, 1, tile, 1});
+  for (uint32_t tile : {512u, 1024u, 2048u, 4096u}) cands.push_back(dc_tune{256, 1, tile, 1});
   clear_error();
   dc_tune best = kDefaultTune;
   double best_us = 1e300;

@@ -30,7 +30,7 @@ constexpr uint32_t kChunk = 16;             // bytes per vector access of the le
 // Compute tiles: a contiguous range of the 16-byte chunks of the leaves laid
 // end to end, at most kTileMaxLeaves leaves (their table sits in LDS) and at
 // most the requested number of chunks. Built on the host per tile size.
-constexpr uint32_t kTileMinChunks = 1024;     // smallest tile size the scratch is sized for
+constexpr uint32_t kTileMinChunks = 512;      // smallest tile size the scratch is sized for
 constexpr uint32_t kTileMaxChunks = 1u << 20;
 constexpr uint32_t kTileMaxLeaves = 256;
 
@@ -219,7 +219,9 @@ hipError_t launch_scalar(const Tables& t, const DevScalar* refs, const DevScalar
                          uint64_t* temps, int update, hipStream_t s);
 hipError_t launch_kick_drift(const Tables& t, const KickDriftArgs& k, hipStream_t s);
 hipError_t launch_resolve_chain(const Tables& t, const ChainArgs& c, hipStream_t s);
-hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint64_t ntiles, bool deref_each, hipStream_t s);
+// every leaf, in the ntiles tiles of tile_chunks chunks listed in the tables
+hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint64_t ntiles, uint32_t tile_chunks,
+                             bool deref_each, hipStream_t s);
 // one FP32/FP64 array at device address `base`, resolved once before the
 // passes (the pointerchain extraction)
 hipError_t launch_stream_resolved(const Tables& t, uint64_t base, uint64_t count, uint32_t kind, const LeafArgs& la,

@@ -831,7 +831,7 @@ hipError_t launch_kick_drift(const Tables& t, const KickDriftArgs& k, hipStream_
   if (k.ntiles == 0) return hipSuccess;
   const uint64_t grid = k.ntiles < (1u << 20) ? k.ntiles : (1u << 20);
   // LDS reserved beyond the kernel's own so that at most five workgroups
-  // share a CU (160 KB of LDS each): five array streams per thread at full
+  // share a CU's 160 KB of LDS: five array streams per thread at full
   // occupancy oversubscribe HBM. Measured on 10,000 MD simulations (19.8 GB
   // per step): 4.07 ms at five workgroups per CU, 4.47 ms at eight.
   constexpr size_t kPerWg = 160 * 1024 / 5 - 2048;
@@ -888,11 +888,16 @@ hipError_t launch_stream_deref(const Tables& t, const HopArgs& h, uint64_t count
   return hipGetLastError();
 }
 
-hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint64_t ntiles, bool deref_each, hipStream_t s) {
+hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint64_t ntiles, uint32_t tile_chunks,
+                             bool deref_each, hipStream_t s) {
   if (ntiles == 0) return hipSuccess;
   const uint64_t grid = ntiles < (1u << 20) ? ntiles : (1u << 20);
+  // RESOLVED: one round per tile for 512- and 1024-chunk tiles (two or four
+  // chunks per thread), rounds of 1024 for larger ones
   if (deref_each)
     hipLaunchKernelGGL((k_leaf_tiles<4, true>), dim3((uint32_t)grid), dim3(256), 0, s, t, la, ntiles);
+  else if (tile_chunks <= 512)
+    hipLaunchKernelGGL((k_leaf_tiles<2, false>), dim3((uint32_t)grid), dim3(256), 0, s, t, la, ntiles);
   else
     hipLaunchKernelGGL((k_leaf_tiles<4, false>), dim3((uint32_t)grid), dim3(256), 0, s, t, la, ntiles);
   return hipGetLastError();

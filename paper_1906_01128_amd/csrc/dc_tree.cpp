@@ -254,10 +254,18 @@ static dc_status plan_chain(dc_plan p, uint64_t root_index, const dc_step* steps
 // one round of four chunks per thread) measured fastest on gfx950 for both
 // cache-resident and HBM-sized trees: many short workgroups keep more
 // requests in flight than fewer long ones.
+// Tile size of the every-leaf kernels: 512-chunk tiles (two chunks per
+// thread) for large leaves streamed from HBM, 1024-chunk tiles (four per
+// thread) otherwise. Measured: large leaves well beyond the 256 MB Infinity
+// Cache (the 1 GB wide tree, ~230 KB per leaf) 5.5 TB/s with 512 against 5.0
+// with 1024; the same shape at 0.28 GB, mostly cache-resident, 5.1 against
+// 5.6; small leaves (the 12 GB MD cells' arrays, ~1.5 KB), whose leaf-table
+// prologue then serves fewer chunks per tile, 4.60 ms against 4.27.
 static uint32_t leaf_tile_for(dc_plan p, int ncu) {
-  (void)p;
   (void)ncu;
-  return kTileMinChunks;
+  const uint64_t nl = p->leaves.size();
+  const bool large = nl && p->total_chunks / nl >= 2048;  // 32 KB per leaf on average
+  return large && p->leaf_bytes >= (512ull << 20) ? 512u : 1024u;
 }
 
 static uint64_t chain_out_bytes(dc_plan p, uint32_t target) {
@@ -387,7 +395,7 @@ dc_status dc_run_kernel(dc_tree t, const dc_kernel_args* a, void* stream) {
     if (deref) DC_TRY(ensure_paths(t, s));
     for (uint32_t it = 0; it < a->iters && e == hipSuccess; it++) {
       la.src_out = (la.out && it > 0) ? 1 : 0;
-      e = launch_leaf_tiles(t->tab, la, t->ntiles, deref, s);
+      e = launch_leaf_tiles(t->tab, la, t->ntiles, t->tile_T, deref, s);
     }
   }
   if (e != hipSuccess) return fail(DC_E_HIP, "kernel launch: %s", hipGetErrorString(e));
