@@ -366,9 +366,17 @@ typedef struct {
   uint32_t launches;       /* 0: one persistent launch; 1: three ordinary launches
                               (relocate, every leaf, reverse relocate), for which
                               block and wg_per_cu are not used */
+  uint32_t spin_limit;     /* persistent launch: polls (about 1 us each) a workgroup
+                              waits for a phase to finish before it records an error
+                              and goes on, so that every launch ends; 0: 2^24 */
 } dc_tune;
 
-enum { DC_BATCH_ATTACH = 1, DC_BATCH_DETACH = 2 };
+/* DC_BATCH_FORCE_WAIT_BOUND is for tests of the error path only: every wait
+ * of the persistent launch waits for one item more than its phase has, so
+ * each wait ends at its bound (keep tune->spin_limit small); the launch still
+ * ends, the tree's leaf values and slots are then unspecified, and the next
+ * check of the tree returns DC_E_STATE. DC_E_INVAL with three launches. */
+enum { DC_BATCH_ATTACH = 1, DC_BATCH_DETACH = 2, DC_BATCH_FORCE_WAIT_BOUND = 4 };
 /* Every structure's relocation and its leaves' kernel (args: RESOLVED,
  * ALL_LEAVES, iters == 1). tune->launches 0: one persistent launch whose
  * workgroups take relocation units, then compute tiles, then (DETACH)

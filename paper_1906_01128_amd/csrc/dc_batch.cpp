@@ -14,7 +14,8 @@
 
 namespace dc {
 
-static const dc_tune kDefaultTune = {256, 4, 1024, 1};
+static const dc_tune kDefaultTune = {256, 4, 1024, 1, 0};
+static const uint32_t kDefaultSpin = 1u << 24;  // polls of a persistent workgroup's wait
 
 static dc_status check_tune(const dc_tune& t) {
   if (t.launches > 1) return fail(DC_E_INVAL, "tune.launches %u (0 or 1)", t.launches);
@@ -129,14 +130,17 @@ static dc_status enqueue_batch(dc_tree t, const LeafArgs& la, const dc_tune& tu,
     if (e == hipSuccess && (flags & DC_BATCH_DETACH)) e = launch_relocate(t->tab, false, s);
   } else {
     e = launch_reset_counters(t->tab.hdr, s);
-    if (e == hipSuccess) e = launch_batch(t->tab, la, flags, tu.block, (uint32_t)t->ctx->ncu * tu.wg_per_cu, ntiles, s);
+    if (e == hipSuccess)
+      e = launch_batch(t->tab, la, flags, tu.block, (uint32_t)t->ctx->ncu * tu.wg_per_cu, ntiles,
+                       tu.spin_limit ? tu.spin_limit : kDefaultSpin, s);
   }
   if (e != hipSuccess) return fail(DC_E_HIP, "batch launch: %s", hipGetErrorString(e));
   return DC_OK;
 }
 
 static dc_status batch_state(dc_tree t, uint32_t flags) {
-  if (flags & ~(uint32_t)(DC_BATCH_ATTACH | DC_BATCH_DETACH)) return fail(DC_E_INVAL, "flags %#x", flags);
+  if (flags & ~(uint32_t)(DC_BATCH_ATTACH | DC_BATCH_DETACH | DC_BATCH_FORCE_WAIT_BOUND))
+    return fail(DC_E_INVAL, "flags %#x", flags);
   if ((flags & DC_BATCH_ATTACH) && t->attached) return fail(DC_E_STATE, "ATTACH on an attached tree");
   if (!(flags & DC_BATCH_ATTACH) && !t->attached) return fail(DC_E_STATE, "the tree is staged: pass ATTACH");
   return DC_OK;
@@ -163,6 +167,8 @@ dc_status dc_batch_run(dc_tree t, const dc_kernel_args* a, const dc_tune* tune, 
   DC_TRY(batch_args(t, a, &la));
   dc_tune tu;
   DC_TRY(resolve_tune(t, tune, &tu));
+  if ((flags & DC_BATCH_FORCE_WAIT_BOUND) && tu.launches != 0)
+    return fail(DC_E_INVAL, "FORCE_WAIT_BOUND needs the persistent launch (tune.launches 0)");
   DC_HIP(hipSetDevice(t->ctx->device));
   DC_TRY(enqueue_batch(t, la, tu, flags, (hipStream_t)stream));
   if (flags & DC_BATCH_DETACH) t->attached = false;
@@ -187,10 +193,10 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
   for (uint32_t block : {256u, 512u})
     for (uint32_t tile : {1024u, 4096u, 16384u})
       for (uint32_t wg : {2u, 4u, 8u}) {
-        dc_tune c{block, wg, tile, 0};
+        dc_tune c{block, wg, tile, 0, 0};
         if (check_tune(c) == DC_OK) cands.push_back(c);
       }
-  for (uint32_t tile : {512u, 1024u, 2048u, 4096u}) cands.push_back(dc_tune{256, 1, tile, 1});
+  for (uint32_t tile : {512u, 1024u, 2048u, 4096u}) cands.push_back(dc_tune{256, 1, tile, 1, 0});
   clear_error();
   dc_tune best = kDefaultTune;
   double best_us = 1e300;

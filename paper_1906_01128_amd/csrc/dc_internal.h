@@ -228,8 +228,9 @@ hipError_t launch_stream_resolved(const Tables& t, uint64_t base, uint64_t count
                                   hipStream_t s);
 hipError_t launch_stream_deref(const Tables& t, const HopArgs& h, uint64_t count, uint32_t kind,
                                const LeafArgs& la, hipStream_t s);
+// spin_limit: polls of a workgroup's wait for a phase before it records kErrSpin
 hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
-                        uint64_t ntiles, hipStream_t s);
+                        uint64_t ntiles, uint32_t spin_limit, hipStream_t s);
 hipError_t launch_reset_counters(DevHeader* hdr, hipStream_t s);
 int device_cu_count();
 

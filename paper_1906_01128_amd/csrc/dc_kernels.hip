@@ -717,12 +717,12 @@ __device__ __forceinline__ uint32_t ld_acquire(uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ void wait_count(DevHeader* hdr, uint32_t* ctr, uint32_t target) {
+__device__ void wait_count(DevHeader* hdr, uint32_t* ctr, uint32_t target, uint32_t spin_limit) {
   if (threadIdx.x == 0) {
     uint32_t spins = 0;
     while (ld_acquire(ctr) < target) {
       __builtin_amdgcn_s_sleep(32);
-      if (++spins > (1u << 24)) {
+      if (++spins > spin_limit) {
         atomicCAS(&hdr->err_code, 0u, (uint32_t)kErrSpin);
         atomicAdd(&hdr->spin_fail, 1u);
         break;
@@ -748,7 +748,7 @@ __device__ __forceinline__ void report_done(uint32_t* ctr, uint32_t n, bool rele
 // a CU runs 2048 threads of the loop at once, as it does for the leaf kernel
 template <int U, int BS>
 __global__ void __launch_bounds__(BS, 8) k_batch(Tables t, LeafArgs la, uint32_t flags, uint64_t ntiles,
-                                                  uint32_t per_item) {
+                                                  uint32_t per_item, uint32_t spin_limit) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ uint32_t s_item;
   DevHeader* hdr = t.hdr;
@@ -756,6 +756,8 @@ __global__ void __launch_bounds__(BS, 8) k_batch(Tables t, LeafArgs la, uint32_t
   const uint32_t nB = (uint32_t)((ntiles + per_item - 1) / per_item);
   const uint32_t nC = (flags & DC_BATCH_DETACH) ? (uint32_t)t.nseg : 0;
   const uint32_t total = nA + nB + nC;
+  // forced error path: each wait waits for one item more than its phase has
+  const uint32_t extra = (flags & DC_BATCH_FORCE_WAIT_BOUND) ? 1u : 0u;
   uint32_t myA = 0, myB = 0;  // items finished and not yet reported
   bool pastA = false, pastB = false, waitedB = false;
   for (;;) {
@@ -778,14 +780,14 @@ __global__ void __launch_bounds__(BS, 8) k_batch(Tables t, LeafArgs la, uint32_t
       lds_barrier();
       myA++;
     } else if (item < nA + nB) {
-      if (myB == 0) wait_count(hdr, &hdr->doneA, nA);
+      if (myB == 0) wait_count(hdr, &hdr->doneA, nA + extra, spin_limit);
       const uint64_t tlo = (uint64_t)(item - nA) * per_item;
       const uint64_t thi = tlo + per_item < ntiles ? tlo + per_item : ntiles;
       for (uint64_t tile = tlo; tile < thi; tile++) leaf_tile<U, false>(t, la, tile, lds);
       myB++;
     } else {
       if (!waitedB) {
-        wait_count(hdr, &hdr->doneB, nB);
+        wait_count(hdr, &hdr->doneB, nB + extra, spin_limit);
         waitedB = true;
       }
       relocate_unit(t, item - nA - nB, false, lds);
@@ -904,7 +906,7 @@ hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint64_t ntile
 }
 
 hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
-                        uint64_t ntiles, hipStream_t s) {
+                        uint64_t ntiles, uint32_t spin_limit, hipStream_t s) {
   if (t.ntypes > kMaxTypes) return hipErrorInvalidValue;
   const size_t rl = reloc_lds_bytes(t.ntypes);
   const size_t lds = kTileLds > rl ? kTileLds : rl;
@@ -917,13 +919,13 @@ hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uin
   // budget of eight waves per SIMD)
   switch (block) {
     case 256:
-      hipLaunchKernelGGL((k_batch<2, 256>), dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
+      hipLaunchKernelGGL((k_batch<2, 256>), dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item, spin_limit);
       break;
     case 512:
-      hipLaunchKernelGGL((k_batch<2, 512>), dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
+      hipLaunchKernelGGL((k_batch<2, 512>), dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item, spin_limit);
       break;
     case 1024:
-      hipLaunchKernelGGL((k_batch<1, 1024>), dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item);
+      hipLaunchKernelGGL((k_batch<1, 1024>), dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item, spin_limit);
       break;
     default:
       return hipErrorInvalidValue;

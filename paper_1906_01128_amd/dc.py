@@ -24,7 +24,7 @@ KIND_NAME = {v: k for k, v in KIND.items()}
 MODE = {"resolved": 0, "deref_each": 1}
 SELECT = {"chain": 0, "all": 1}
 COPY_LEAVES, COPY_SCALARS = 1, 2
-BATCH_ATTACH, BATCH_DETACH = 1, 2
+BATCH_ATTACH, BATCH_DETACH, BATCH_FORCE_WAIT_BOUND = 1, 2, 4
 
 u32, u64, i32, vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p
 
@@ -80,7 +80,7 @@ class KernelArgs(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("block", u32), ("wg_per_cu", u32), ("tile_chunks", u32), ("launches", u32)]
+    _fields_ = [("block", u32), ("wg_per_cu", u32), ("tile_chunks", u32), ("launches", u32), ("spin_limit", u32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -406,10 +406,14 @@ class Tree:
         _check(load().dc_scalar_update(self.h, arr, len(refs), _dev_ptr(temps), _stream_ptr(stream)),
                "dc_scalar_update")
 
-    def batch_run(self, a=1.0001, b=0.5, tune=None, attach=True, detach=False, out=None, stream=None):
+    def batch_run(self, a=1.0001, b=0.5, tune=None, attach=True, detach=False, out=None, stream=None,
+                  force_wait_bound=False):
+        """force_wait_bound: the error path of the persistent launch's waits
+        (tests only; see DC_BATCH_FORCE_WAIT_BOUND)."""
         ka = _kargs(mode="resolved", select="all", iters=1, a=a, b=b, out=out)
         tu = _tune(tune)
-        flags = (BATCH_ATTACH if attach else 0) | (BATCH_DETACH if detach else 0)
+        flags = ((BATCH_ATTACH if attach else 0) | (BATCH_DETACH if detach else 0) |
+                 (BATCH_FORCE_WAIT_BOUND if force_wait_bound else 0))
         _check(load().dc_batch_run(self.h, ctypes.byref(ka), ctypes.byref(tu) if tu else None, flags,
                                    _stream_ptr(stream)), "dc_batch_run")
 
@@ -492,6 +496,7 @@ def _tune(tune):
     tu.wg_per_cu = tune.get("wg_per_cu", 0)
     tu.tile_chunks = tune.get("tile_chunks", 0)
     tu.launches = tune.get("launches", 0)
+    tu.spin_limit = tune.get("spin_limit", 0)
     return tu
 
 

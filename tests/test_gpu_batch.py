@@ -128,3 +128,29 @@ def test_batch_md_full_size(ctx):
     for lo in range(0, len(want), step):
         assert np.array_equal(got[lo:lo + step], want[lo:lo + step]), f"md full arena differs in GiB {lo >> 30}"
     c.tree.check()
+
+
+def test_forced_wait_bound_is_reported_and_the_launch_ends(ctx):
+    """The persistent launch's waits are bounded. Forced (from the host) to
+    wait for one item more than each phase has, every wait ends at a small
+    bound, the launch ends, and the next check of the tree reports the error;
+    a fresh copy then runs exactly as before."""
+    from paper_1906_01128_amd import dc
+    t = fx.md(seed=5, nsims=60, cells_lo=1, cells_hi=40, mean_atoms=5)
+    c = Copy(ctx, t, relocate=False)
+    tune = dict(block=256, wg_per_cu=1, tile_chunks=1024, launches=0, spin_limit=64)
+    print(f"[gpu] forced wait bound: {tune}", flush=True)
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=tune, force_wait_bound=True)
+    torch.cuda.synchronize()
+    with pytest.raises(dc.DcError) as e:
+        c.tree.check()
+    assert e.value.name == "STATE" and "wait bound" in str(e.value)
+    c2 = Copy(ctx, t, relocate=False)
+    # three launches have no waits to force
+    with pytest.raises(dc.DcError) as e:
+        c2.tree.batch_run(attach=True, detach=True, tune=dict(tile_chunks=1024, launches=1), force_wait_bound=True)
+    assert e.value.name == "INVAL"
+    want = _staged_after_kernel(c2, 1)
+    c2.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=dict(tune, spin_limit=0))
+    assert_same_bytes(c2.device_arena(), want, "persistent launch after a forced wait bound")
+    c2.tree.check()
