@@ -474,6 +474,9 @@ def bench_batched(args, torch, dc):
     step_s = [a.elapsed_time(b) / 1e3 for a, b in recs]
     # the same work as separate launches: attach, one pass over every leaf, detach
     phases = {"attach": [], "leaf_tiles": [], "detach": []}
+    tree.attach()   # untimed: builds the tile list of the every-leaf kernel if the graph's differs
+    tree.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.5)
+    tree.detach()
     for _ in range(3):
         e = [ev() for _ in range(4)]
         e[0].record(s)
@@ -501,6 +504,20 @@ def bench_batched(args, torch, dc):
         kd.append(e0.elapsed_time(e1) / 1e3)
     tree.check()
     tree.detach()
+    # the same step as one persistent launch, in its best measured shape, for
+    # comparison when the autotuner picked three launches (last: it rebuilds
+    # the tile list for its own tile size)
+    pt = dict(block=1024, wg_per_cu=2, tile_chunks=16384, launches=0)
+    tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=pt)
+    pers = []
+    for _ in range(3):
+        e0, e1 = ev(), ev()
+        e0.record(s)
+        tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=pt)
+        e1.record(s)
+        torch.cuda.synchronize()
+        pers.append(e0.elapsed_time(e1) / 1e3)
+    tree.check()
     kd_bytes = 40 * (info.leaf_bytes // 24)    # per double of x: read x, v, f; write x, v
     kd_gbps = kd_bytes / pct(kd, 50) / 1e9
     plain = _batched_vs_plain(torch, dc, ctx, t, tune, nsub=500)
@@ -527,6 +544,8 @@ def bench_batched(args, torch, dc):
                          "avg_launch_us": round(1e6 * k_s, 1)},
             "latency_ms": {"p50": round(1e3 * pct(step_s, 50), 3), "p99": round(1e3 * pct(step_s, 99), 3)},
             "separate_launches_ms": {k: round(pct(v_, 50), 3) for k, v_ in phases.items()},
+            "persistent_launch": {"tune": pt, "ms": round(1e3 * pct(pers, 50), 3),
+                                  "over_step": round(pct(pers, 50) / pct(step_s, 50), 3)},
             "one_structure_per_call": plain,
             "kick_drift": {"kernel": "k_kick_drift", "ms": round(1e3 * pct(kd, 50), 3),
                            "bytes_per_launch": kd_bytes, "achieved_GBps": round(kd_gbps, 1),

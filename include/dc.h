@@ -396,7 +396,9 @@ dc_status dc_autotune(dc_tree tree, const dc_kernel_args* args, uint32_t reps, d
 /* Captures dc_batch_run(tree, args, tune, flags) into a HIP graph; optionally
  * preceded by the host-to-device transfer of the staged image (upload != 0,
  * which keeps a pinned copy of the whole image) and followed by the transfer
- * back of the arena into pinned memory (download != 0). */
+ * back of the arena into pinned memory (download != 0). dc_graph_launch
+ * replays it; if a call with another tile size has rebuilt the tree's tile
+ * list since the capture, the launch first rebuilds the captured one. */
 dc_status dc_graph_create(dc_tree tree, const dc_kernel_args* args, const dc_tune* tune, uint32_t flags,
                           int upload, int download, dc_graph* out);
 dc_status dc_graph_launch(dc_graph graph, void* stream);

@@ -152,6 +152,7 @@ using namespace dc;
 
 struct dc_graph_s {
   dc_tree tree = nullptr;
+  uint32_t tile_T = 0;      // tile size of the tile list the captured launches read
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   uint8_t* up = nullptr;    // pinned staged image
@@ -259,6 +260,7 @@ dc_status dc_graph_create(dc_tree t, const dc_kernel_args* a, const dc_tune* tun
   if (!p->leaves.empty()) {
     dc_status st = tree_ensure_tiles(t, tu.tile_chunks, cs);
     if (st != DC_OK) return cleanup(st);
+    g->tile_T = tu.tile_chunks;
   }
   if (upload) {
     if (hipHostMalloc((void**)&g->up, std::max<uint64_t>(p->arena_bytes, 1), hipHostMallocDefault) != hipSuccess)
@@ -287,6 +289,10 @@ dc_status dc_graph_launch(dc_graph g, void* stream) {
   if (!g || !g->exec) return fail(DC_E_INVAL, "dc_graph_launch: null graph");
   if (g->tree->attached) return fail(DC_E_STATE, "dc_graph_launch needs the tree staged");
   DC_HIP(hipSetDevice(g->tree->ctx->device));
+  // the captured launches carry the tile count of the list built at capture;
+  // a call with another tile size since then rebuilt the list, so rebuild it
+  // back (outside the graph) before the replay reads it
+  if (g->tile_T && g->tree->tile_T != g->tile_T) DC_TRY(tree_ensure_tiles(g->tree, g->tile_T, (hipStream_t)stream));
   DC_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
   return DC_OK;
 }

@@ -83,6 +83,25 @@ def test_graph_replays(ctx, launches):
     g.close()
 
 
+@pytest.mark.parametrize("launches", [0, 1])
+def test_graph_replay_after_another_tile_size(ctx, launches):
+    """A graph replays the tile count it was captured with: calls with other
+    tile sizes in between rebuild the tree's tile list, and the replay must
+    restore its own before it runs."""
+    t = fx.md(seed=9, nsims=40, cells_lo=2, cells_hi=30, mean_atoms=8)
+    c = Copy(ctx, t, relocate=False)
+    g = c.tree.graph(a=1.0001, b=0.5, tune=dict(tile_chunks=1024, launches=launches))
+    passes = 0
+    for other in (4096, 512, 1 << 16):
+        c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=dict(tile_chunks=other, launches=launches))
+        g.launch()
+        passes += 2
+        torch.cuda.synchronize()
+        assert_same_bytes(c.device_arena(), _staged_after_kernel(c, passes), f"replay after tiles of {other}")
+    c.tree.check()
+    g.close()
+
+
 def test_graph_with_upload_restarts_from_image(ctx):
     t = fx.md(seed=7, nsims=30, cells_lo=2, cells_hi=20, mean_atoms=8)
     c = Copy(ctx, t, relocate=False)
