@@ -345,7 +345,8 @@ enum { DC_COPY_LEAVES = 1, DC_COPY_SCALARS = 2 };
  * updated (waits for earlier work on `stream`). */
 dc_status dc_copy_back(dc_tree tree, uint32_t flags, void* stream);
 
-/* Releases the tree's host-side state (not the caller's device buffers). */
+/* Releases the tree's host-side state (not the caller's device buffers).
+ * Destroy the tree's graphs first: a graph refers to its tree. */
 dc_status dc_tree_release(dc_tree tree);
 /* Waits for `stream`, then reports a device-side error recorded by earlier
  * passes of this tree (DC_E_STATE) or DC_OK. */
@@ -402,6 +403,7 @@ dc_status dc_autotune(dc_tree tree, const dc_kernel_args* args, uint32_t reps, d
 dc_status dc_graph_create(dc_tree tree, const dc_kernel_args* args, const dc_tune* tune, uint32_t flags,
                           int upload, int download, dc_graph* out);
 dc_status dc_graph_launch(dc_graph graph, void* stream);
+/* Destroys a graph (before its tree is released). */
 dc_status dc_graph_destroy(dc_graph graph);
 
 /* ---- served form ---------------------------------------------------------------- */
