@@ -137,7 +137,7 @@ void copy_stream(void* dst, const void* src, uint64_t n) {
 // ---- staging ----------------------------------------------------------------------------
 
 // Writes destination range [lo, hi) into buf: the bytes of every piece that
-// overlaps it, zeros elsewhere. Split across the pool in ~4 MiB parts.
+// overlaps it, zeros elsewhere. Split across the pool in 1 MiB parts.
 static void pack_range(dc_ctx ctx, uint8_t* buf, uint64_t lo, uint64_t hi, const PieceSource& src) {
   const uint64_t part = 1ull << 20;
   const int nparts = (int)((hi - lo + part - 1) / part);
