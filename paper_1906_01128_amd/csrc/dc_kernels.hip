@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(256) k_leaf_tiles(Tables t, LeafArgs la, uint6
 // ---- molecular dynamics: kick then drift on sibling leaves ------------------------------
 //
 // One tile: a range of 16-byte chunks of the elements' arrays laid end to
-// end (each element contributes ceil(count / 2) chunks; 512 per tile), at
+// end (each element contributes ceil(count / 2) chunks; 256 per tile), at
 // most kTileMaxLeaves elements. The element's three array addresses are read once
 // per tile from its relocated slots (the resolved form of Section 3) and
 // checked against the arena; per chunk: v = fma(f, dt/m, v), x = fma(v, dt, x).
@@ -832,13 +832,11 @@ hipError_t launch_scalar(const Tables& t, const DevScalar* refs, const DevScalar
 hipError_t launch_kick_drift(const Tables& t, const KickDriftArgs& k, hipStream_t s) {
   if (k.ntiles == 0) return hipSuccess;
   const uint64_t grid = k.ntiles < (1u << 20) ? k.ntiles : (1u << 20);
-  // LDS reserved beyond the kernel's own so that at most five workgroups
-  // share a CU's 160 KB of LDS: five array streams per thread at full
-  // occupancy oversubscribe HBM. Measured on 10,000 MD simulations (19.8 GB
-  // per step): 4.07 ms at five workgroups per CU, 4.47 ms at eight.
-  constexpr size_t kPerWg = 160 * 1024 / 5 - 2048;
-  static_assert(kPerWg > 160 * 1024 / 6 && kPerWg > kKdLds, "five workgroups per CU");
-  hipLaunchKernelGGL(k_kick_drift<2>, dim3((uint32_t)grid), dim3(256), kPerWg - kKdLds, s, t, k);
+  // one chunk per thread (256-chunk tiles), at full occupancy: measured on
+  // 10,000 MD simulations (19.8 GB per step) 3.86 ms, against 4.07 ms with two
+  // chunks per thread at five workgroups per CU (4.47 at eight) and 4.3-4.7 ms
+  // with four
+  hipLaunchKernelGGL(k_kick_drift<1>, dim3((uint32_t)grid), dim3(256), 0, s, t, k);
   return hipGetLastError();
 }
 

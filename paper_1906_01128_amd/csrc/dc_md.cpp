@@ -62,10 +62,10 @@ static dc_status kd_build(dc_tree t, const dc_kick_drift_args* a, std::vector<De
   pre.resize(tri.size() + 1);
   pre[0] = 0;
   for (size_t i = 0; i < tri.size(); i++) pre[i + 1] = pre[i] + (tri[i].count + 1) / 2;
-  // tiles of at most 512 chunks (one round of two chunks per thread) and
-  // kTileMaxLeaves elements: measured 4.5 TB/s on 4000 MD simulations against
-  // 4.1-4.3 with 1024-4096-chunk tiles
-  const uint64_t T = 512, total = pre.back(), ne = tri.size();
+  // tiles of at most 256 chunks (one round of one chunk per thread) and
+  // kTileMaxLeaves elements; on 10,000 MD simulations 5.1 TB/s against 4.9 with
+  // 512-chunk tiles of two chunks per thread and 4.2-4.6 with 1024
+  const uint64_t T = 256, total = pre.back(), ne = tri.size();
   uint64_t l = 0;
   for (uint64_t c = 0; c < total;) {
     while (pre[l + 1] <= c) l++;
