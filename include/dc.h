@@ -132,9 +132,15 @@ typedef struct {
  * a pool of host threads for packing. Errors: DC_E_NOMEM if the pinned
  * staging cannot be allocated, DC_E_HIP. */
 dc_status dc_ctx_create(int device, dc_ctx* out);
+/* Frees the context's staging and threads, after every tree, plan and server
+ * made with it has been released. Errors: DC_E_INVAL for NULL. */
 dc_status dc_ctx_destroy(dc_ctx ctx);
 
+/* An empty schema; dc_schema_describe adds its struct types. Errors:
+ * DC_E_INVAL for a NULL out. */
 dc_status dc_schema_create(dc_schema* out);
+/* Frees a schema, after the plans and servers made from it. Errors:
+ * DC_E_INVAL for NULL. */
 dc_status dc_schema_destroy(dc_schema schema);
 
 /* Registers a struct type of `size` bytes and alignment `align` with its
@@ -175,10 +181,13 @@ dc_status dc_plan_create(dc_ctx ctx, dc_schema schema, uint32_t root_type, const
 dc_status dc_plan_create_selective(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* const* roots,
                                    uint64_t nroots, uint64_t align, const uint32_t* follow, uint32_t nfollow,
                                    dc_plan* out, uint64_t* arena_bytes, uint64_t* scratch_bytes);
+/* Frees a plan, after the trees made from it. Errors: DC_E_INVAL for NULL. */
 dc_status dc_plan_destroy(dc_plan plan);
+/* The plan's sizes and counts. Errors: DC_E_INVAL for a NULL argument. */
 dc_status dc_plan_query(dc_plan plan, dc_plan_info* out);
 /* Copies up to cap placed objects, in arena order, into out; *n receives the
- * total number of objects. */
+ * total number of objects. Errors: DC_E_INVAL for a NULL plan or n, or a
+ * NULL out with cap > 0. */
 dc_status dc_plan_objects(dc_plan plan, dc_object* out, uint64_t cap, uint64_t* n);
 
 /* The deep copy: packs the host tree into pinned staging in arena order
@@ -195,7 +204,7 @@ dc_status dc_deep_copy_to_device(dc_ctx ctx, dc_plan plan, void* d_arena, uint64
 
 /* Like dc_deep_copy_to_device but without the relocation: the arena holds
  * the host bytes verbatim (host addresses in every pointer member) until
- * dc_attach or dc_batch_run relocates it. */
+ * dc_attach or dc_batch_run relocates it. Errors: as dc_deep_copy_to_device. */
 dc_status dc_stage_to_device(dc_ctx ctx, dc_plan plan, void* d_arena, uint64_t arena_bytes, void* d_scratch,
                              uint64_t scratch_bytes, void* stream, dc_tree* out);
 
@@ -205,7 +214,8 @@ dc_status dc_stage_to_device(dc_ctx ctx, dc_plan plan, void* d_arena, uint64_t a
  * addresses back to the host addresses they came from. The tree must be in
  * the opposite state (DC_E_STATE otherwise). Asynchronous on `stream`; an
  * address that is not a planned array start is counted in a device error
- * flag that the next synchronous call reports as DC_E_STATE. */
+ * flag that the next synchronous call reports as DC_E_STATE. Errors also:
+ * DC_E_INVAL for a NULL or released tree, DC_E_HIP. */
 dc_status dc_attach(dc_tree tree, void* stream);
 dc_status dc_detach(dc_tree tree, void* stream);
 
@@ -237,11 +247,14 @@ dc_status dc_chain_query(dc_schema schema, uint32_t root_type, const void* root,
 dc_status dc_chain_to_device(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* root, const dc_step* steps,
                              uint32_t nsteps, void* d_buf, uint64_t buf_bytes, void* stream, dc_chain* out);
 /* `iters` passes of x = fma(x, a, b) (FP64: a, b; FP32: af, bf) over an array
- * placed by dc_chain_to_device. Asynchronous on `stream`. */
+ * placed by dc_chain_to_device. Asynchronous on `stream`. Errors: DC_E_INVAL
+ * for a NULL context or chain or a kind other than FP32/FP64, DC_E_HIP. */
 dc_status dc_chain_run_kernel(dc_ctx ctx, const dc_chain* c, uint32_t iters, double a, double b, float af, float bf,
                               void* stream);
 /* Transfers such an array back into the host array the same chain ends in.
- * Returns when the host array is updated. */
+ * Returns when the host array is updated. Errors: as dc_chain_query;
+ * DC_E_STATE if the chain now ends in an array of another count or kind than
+ * the device copy (the host tree changed); DC_E_HIP. */
 dc_status dc_chain_copy_back(dc_ctx ctx, dc_schema schema, uint32_t root_type, const void* root, const dc_step* steps,
                              uint32_t nsteps, const dc_chain* c, void* stream);
 
@@ -333,7 +346,8 @@ typedef struct {
 
 dc_status dc_run_kernel(dc_tree tree, const dc_kernel_args* args, void* stream);
 
-/* Bytes of the out-of-place leaf image for args (select and chain). */
+/* Bytes of the out-of-place leaf image for args (select and chain). Errors:
+ * DC_E_INVAL for a NULL argument or an invalid chain. */
 dc_status dc_out_bytes(dc_tree tree, const dc_kernel_args* args, uint64_t* out);
 
 /* ---- copy back (Algorithm 2 step 5) ------------------------------------------------ */
@@ -342,17 +356,21 @@ enum { DC_COPY_LEAVES = 1, DC_COPY_SCALARS = 2 };
 /* Transfers the arena back and writes into the host tree: LEAVES = every
  * primitive array; SCALARS = the non-pointer bytes of every struct element.
  * Host pointer members are never written. Returns when the host tree is
- * updated (waits for earlier work on `stream`). */
+ * updated (waits for earlier work on `stream`). Errors: DC_E_INVAL for a NULL
+ * or released tree or unknown flags, DC_E_STATE when the device check after
+ * the transfer fails (the host tree has been written), DC_E_HIP. */
 dc_status dc_copy_back(dc_tree tree, uint32_t flags, void* stream);
 
 /* Releases the tree's host-side state (not the caller's device buffers).
- * Destroy the tree's graphs first: a graph refers to its tree. */
+ * Destroy the tree's graphs first: a graph refers to its tree. Errors:
+ * DC_E_INVAL for NULL. */
 dc_status dc_tree_release(dc_tree tree);
 /* Waits for `stream`, then reports a device-side error recorded by earlier
  * passes of this tree (DC_E_STATE) or DC_OK. */
 dc_status dc_tree_check(dc_tree tree, void* stream);
 /* The layout of a deep copy on the device: as dc_plan_objects, except that
- * `offset` is replaced by the object's device address (d_arena + offset). */
+ * `offset` is replaced by the object's device address (d_arena + offset).
+ * Errors: DC_E_INVAL for a NULL or released tree, as dc_plan_objects. */
 dc_status dc_tree_objects(dc_tree tree, dc_object* out, uint64_t cap, uint64_t* n);
 
 /* ---- batched form ------------------------------------------------------------------ */
@@ -391,7 +409,10 @@ dc_status dc_batch_run(dc_tree tree, const dc_kernel_args* args, const dc_tune* 
  * tree (which leaves its leaf values changed: deep copy again before a run
  * whose values matter) and returns the fastest; the choice is cached on disk
  * keyed by device and workload shape (DC_TUNE_CACHE, default
- * ~/.cache/dc_tune.json). */
+ * ~/.cache/dc_tune.json). Errors: DC_E_INVAL for a NULL argument or args
+ * other than RESOLVED, ALL_LEAVES, one pass; DC_E_STATE if the tree is
+ * attached or a device check fails; DC_E_RANGE for a d_out too small or
+ * misaligned; DC_E_HIP. */
 dc_status dc_autotune(dc_tree tree, const dc_kernel_args* args, uint32_t reps, dc_tune* out);
 
 /* Captures dc_batch_run(tree, args, tune, flags) into a HIP graph; optionally
@@ -399,7 +420,11 @@ dc_status dc_autotune(dc_tree tree, const dc_kernel_args* args, uint32_t reps, d
  * which keeps a pinned copy of the whole image) and followed by the transfer
  * back of the arena into pinned memory (download != 0). dc_graph_launch
  * replays it; if a call with another tile size has rebuilt the tree's tile
- * list since the capture, the launch first rebuilds the captured one. */
+ * list since the capture, the launch first rebuilds the captured one.
+ * Errors (create): DC_E_INVAL for flags other than ATTACH|DETACH or bad args
+ * or tune, DC_E_STATE if the tree is attached, DC_E_NOMEM for the pinned
+ * image, DC_E_HIP. Errors (launch): DC_E_INVAL for NULL, DC_E_STATE if the
+ * tree is attached, DC_E_HIP. */
 dc_status dc_graph_create(dc_tree tree, const dc_kernel_args* args, const dc_tune* tune, uint32_t flags,
                           int upload, int download, dc_graph* out);
 dc_status dc_graph_launch(dc_graph graph, void* stream);
@@ -445,14 +470,24 @@ typedef struct {
   uint64_t resident_bytes, peak_bytes;
 } dc_server_stats;
 
+/* A server on ctx's device for structures of `schema`: one device allocation
+ * of cfg->budget_bytes (at least 1 MiB), two contexts of its own (pinned
+ * staging for each direction) and its two threads. Errors: DC_E_INVAL for a
+ * NULL argument or a budget under 1 MiB, DC_E_NOMEM, DC_E_HIP (the budget's
+ * allocation or a stream). */
 dc_status dc_server_create(dc_ctx ctx, dc_schema schema, const dc_server_config* cfg, dc_server* out);
 /* Queues a job (the structure is read when the job is admitted, so it must
  * stay unchanged until its result arrives); returns its id. DC_E_BUDGET if
  * it can never fit the budget. */
 dc_status dc_server_submit(dc_server srv, const dc_request* req, uint64_t* id);
-/* Waits for job `id` (timeout_s < 0: forever) and returns its result. */
+/* Waits for job `id` (timeout_s < 0: forever) and returns its result.
+ * Errors: DC_E_INVAL for a NULL argument or an unknown id, DC_E_STATE if the
+ * job has not finished within timeout_s, else the job's own status. */
 dc_status dc_server_wait(dc_server srv, uint64_t id, double timeout_s, dc_result* out);
+/* Counters since creation. Errors: DC_E_INVAL for a NULL argument. */
 dc_status dc_server_stats_get(dc_server srv, dc_server_stats* out);
+/* Lets admitted jobs finish, stops the threads and frees the budget and the
+ * server's contexts. Errors: DC_E_INVAL for NULL. */
 dc_status dc_server_destroy(dc_server srv);
 
 /* ---- misc ------------------------------------------------------------------------ */
