@@ -117,6 +117,20 @@ def test_pointerchain_errors(ctx):
         dc.ChainCopy(ctx, schema, 0, t.roots[0], [(1, 0), (1, 0), (0, 0)], buf[8:])
     cc = dc.ChainCopy(ctx, schema, 0, t.roots[0], [(1, 0), (1, 0), (0, 0)], buf)
     assert cc.count == 100
+    # the host chain changes shape after the transfer: the copy back refuses
+    # (Linear node: i32 nA, i32 nLnext, double* A, node* Lnext)
+    l1 = ctypes.c_uint64.from_address(t.roots[0] + 16).value
+    l2 = ctypes.c_uint64.from_address(l1 + 16).value
+    na = ctypes.c_int32.from_address(l2)
+    assert na.value == 100
+    na.value = 50
+    try:
+        with pytest.raises(dc.DcError) as e:
+            cc.copy_back()
+        assert e.value.name == "STATE"
+    finally:
+        na.value = 100
+    cc.copy_back()
 
 
 # ---- the sweep's configurations: Dense chains and Linear allinit -----------------------

@@ -99,6 +99,29 @@ def test_budget_admission_and_eviction(ctx):
     srv.close()
 
 
+def test_wait_timeout_and_unknown_id(ctx):
+    """A wait that times out reports DC_E_STATE and leaves the job running;
+    waiting again returns its result. An id never issued is DC_E_INVAL."""
+    from paper_1906_01128_amd import dc
+    t = fx.broom(seed=9300, d_lo=4, d_hi=4, f_lo=16, f_hi=16, bytes_lo=16 << 20, bytes_hi=32 << 20)
+    schema = dc.Schema(t.types)
+    srv = dc.Server(ctx, schema, budget_bytes=4 << 30, max_inflight=2, nstreams=1)
+    need = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 0).out_bytes("all")
+    buf = np.zeros(need, np.uint8)
+    rid = srv.submit(t.root_type, t.roots[0], buf.ctypes.data, buf.nbytes, *AB[0])
+    # hundreds of MB in and out cannot be done at once
+    with pytest.raises(dc.DcError) as e:
+        srv.wait(rid, timeout=0.0)
+    assert e.value.name == "STATE"
+    res = srv.wait(rid, timeout=120.0)
+    assert res.status == 0
+    assert np.array_equal(buf, _expected(t, *AB[0]))
+    with pytest.raises(dc.DcError) as e:
+        srv.wait(rid + 1000, timeout=0.0)
+    assert e.value.name == "INVAL"
+    srv.close()
+
+
 @pytest.mark.slow
 def test_served_full_size_sampled(ctx):
     """The served workload's full distribution (leaf bytes up to 256 MiB, fan-out
