@@ -713,14 +713,18 @@ __global__ void __launch_bounds__(256) k_kick_drift(Tables t, KickDriftArgs k) {
 // when it moves past that phase: one device-scope release per workgroup
 // rather than one per item (a release writes back the XCD's L2).
 
-__device__ __forceinline__ uint32_t ld_acquire(uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// The poll is relaxed and one acquire fence follows the wait: an acquire
+// load at device scope invalidates the XCD's L2 on every poll, which, from
+// hundreds of waiting workgroups, keeps dropping the lines the working ones
+// stream through.
+__device__ __forceinline__ uint32_t ld_relaxed(uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ void wait_count(DevHeader* hdr, uint32_t* ctr, uint32_t target, uint32_t spin_limit) {
   if (threadIdx.x == 0) {
     uint32_t spins = 0;
-    while (ld_acquire(ctr) < target) {
+    while (ld_relaxed(ctr) < target) {
       __builtin_amdgcn_s_sleep(32);
       if (++spins > spin_limit) {
         atomicCAS(&hdr->err_code, 0u, (uint32_t)kErrSpin);
@@ -728,6 +732,9 @@ __device__ void wait_count(DevHeader* hdr, uint32_t* ctr, uint32_t target, uint3
         break;
       }
     }
+    // synchronizes with the release of the increments the poll has read;
+    // the barrier then orders the other threads after it
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
