@@ -1,21 +1,23 @@
 """Benchmark of the deep-copy + pointer-chain kernel hot path on one MI355X.
 
-Default workload (the Linear chain of the paper's Section 4.1 at its largest
-single-structure size): 8 nested nodes, only the last one owning an FP64
-payload of 2^24 elements; a step is
+Default workload (the batched MD workload, the largest single-GPU
+configuration): 10,000 independent simulations, each a struct pointing to
+an array of cells (uniform 8..512 per simulation), each cell pointing to
+three double3 arrays (positions, velocities, forces) of Poisson(64) atoms;
+~7.75 M arrays, ~12 GB. A step is one replay of a HIP graph that
 
-    attach (device relocation of every pointer)          -- Figure 2 (d)
-    100 passes of x = fma(x, 1.0001, 0.5), address resolved once
-                                                      -- pointerchain, Sec. 3
-    100 passes of the same with the chain walked on every element access
-    detach (demarshalling: pointers back to host values)
+    attaches every pointer of every structure    -- Figure 2 (d), Algorithm 1
+    runs x = fma(x, 1.0001, 0.5) over every leaf, each leaf's address read
+    once from its relocated parent slot          -- pointerchain, Section 3
+    detaches every pointer again (demarshalling)
 
-with the marshalled image already resident in HBM when the timed region
-starts. `value` is the algorithmic bytes of a step over its time. The
-host-link part of the deep copy (pack + host-to-device + copy back) is timed
-separately and reported as `host_link` / `end_to_end`, never as `value`.
+in the form the autotuner measured fastest, with the marshalled image
+already resident in HBM when the timed region starts. `value` is the
+algorithmic bytes of a step over its time. The host-link part of the deep
+copy (pack + host-to-device + attach, and the copy back) is timed
+separately and reported as `host_link`, never as `value`.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload linear|wide|batched|served|sweep]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|linear|wide|plain|served|sweep]
 """
 import argparse
 import ctypes
@@ -57,13 +59,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="linear",
+    ap.add_argument("--workload", default="batched",
                     choices=["linear", "plain", "wide", "batched", "served", "sweep", "copycal"])
     ap.add_argument("--full", action="store_true",
                     help="sweep: the paper's full size range; served: 2000 jobs, leaves up to 256 MiB")
     ap.add_argument("--passes", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-link", action="store_true", help="skip the host-link measurements")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="batched: skip the comparisons beside the timed step (forms, kick-drift, linear chain)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -258,16 +262,19 @@ def bench_linear(args, torch, dc):
             h2d.append(plan.arena_bytes / (t1 - t0) / 1e9)
             d2h.append(leaf / (t3 - t2) / 1e9)
             e2e.append(t3 - t0)
-        out["host_link"] = {"h2d_GBps": round(max(h2d), 2), "d2h_GBps": round(max(d2h), 2),
+        mh, md_ = pct(h2d, 50), pct(d2h, 50)
+        out["host_link"] = {"what": f"median of {LINK_REPS} deep copies after {LINK_WARMUP} untimed",
+                            "h2d_GBps": round(mh, 2), "d2h_GBps": round(md_, 2),
+                            "h2d_runs": [round(x, 2) for x in h2d], "d2h_runs": [round(x, 2) for x in d2h],
                             "pinned_peak_h2d_GBps": round(peak["h2d"], 2), "pinned_peak_d2h_GBps": round(peak["d2h"], 2),
                             "spec_peak_GBps": LINK_PEAK_GBPS,
-                            "h2d_frac_of_spec": round(max(h2d) / LINK_PEAK_GBPS, 4),
-                            "d2h_frac_of_spec": round(max(d2h) / LINK_PEAK_GBPS, 4),
-                            "h2d_frac_of_measured": round(max(h2d) / peak["h2d"], 4),
-                            "d2h_frac_of_measured": round(max(d2h) / peak["d2h"], 4)}
+                            "h2d_frac_of_spec": round(mh / LINK_PEAK_GBPS, 4),
+                            "d2h_frac_of_spec": round(md_ / LINK_PEAK_GBPS, 4),
+                            "h2d_frac_of_measured": round(mh / peak["h2d"], 4),
+                            "d2h_frac_of_measured": round(md_ / peak["d2h"], 4)}
         job_bytes = plan.arena_bytes + leaf + 2 * kernel_bytes
         out["end_to_end"] = {"what": "pack + H2D + attach + both kernels + copy back, host buffers in and out",
-                             "GBps": round(job_bytes / min(e2e) / 1e9, 2),
+                             "GBps": round(job_bytes / pct(e2e, 50) / 1e9, 2),
                              "p50_ms": round(1e3 * pct(e2e, 50), 3), "p99_ms": round(1e3 * pct(e2e, 99), 3)}
     return out
 
@@ -342,8 +349,8 @@ def _bench_wide(args, torch, dc, hi):
             tr.release()
             if r >= LINK_WARMUP:
                 ts.append((t1 - t0, t2 - t1, t3 - t2))
-        h2d = plan.arena_bytes / min(a for a, _, _ in ts) / 1e9
-        d2h = info.leaf_bytes / min(c for _, _, c in ts) / 1e9
+        h2d = plan.arena_bytes / pct([a for a, _, _ in ts], 50) / 1e9
+        d2h = info.leaf_bytes / pct([c for _, _, c in ts], 50) / 1e9
         out["host_link"] = {"h2d_GBps": round(h2d, 2), "h2d_frac_of_spec": round(h2d / LINK_PEAK_GBPS, 4),
                             "d2h_GBps": round(d2h, 2), "d2h_frac_of_spec": round(d2h / LINK_PEAK_GBPS, 4),
                             "end_to_end_ms_p50": round(1e3 * pct([a + b + c for a, b, c in ts], 50), 3)}
@@ -394,6 +401,8 @@ def _batched_vs_plain(torch, dc, ctx, t, tune, nsub):
     arena = torch.empty(plan.arena_bytes, dtype=torch.uint8, device="cuda")
     scratch = torch.empty(plan.scratch_bytes, dtype=torch.uint8, device="cuda")
     tree = dc.Tree(ctx, plan, arena, scratch, relocate=False)
+    if tune is None:   # this plan's own choice
+        tune = tree.autotune(reps=2)
     g = tree.graph(a=1.0001, b=0.5, tune=tune)
     g.launch()
     e0, e1 = ev(), ev()
@@ -428,27 +437,122 @@ def _batched_vs_plain(torch, dc, ctx, t, tune, nsub):
     plain_ms = e0.elapsed_time(e1)
     for _, _, _, tr in trees:
         tr.release()
-    return {"simulations": nsub, "batched_ms": round(batched_ms, 3), "per_structure_ms": round(plain_ms, 3),
+    return {"simulations": nsub, "tune": tune, "batched_ms": round(batched_ms, 3), "per_structure_ms": round(plain_ms, 3),
             "batched_GBps": round(2 * leaf / batched_ms / 1e6, 1), "per_structure_GBps": round(2 * leaf / plain_ms / 1e6, 1),
             "speedup": round(plain_ms / batched_ms, 2)}
 
 
+def host_cpu():
+    """Model name and the number of CPUs this process may run on."""
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, n
+
+
+def md_step_bytes(info):
+    """Algorithmic bytes of one batched step: every leaf byte read and written
+    once, and per relocation (attach, then detach) 8 B read + 8 B written per
+    non-null slot, 8 B read per null slot and 16 B per target entry."""
+    return 2 * info.leaf_bytes + 2 * (info.nslots_nonnull * 16 + info.nslots * 8 + info.nobjects * 16)
+
+
+def cpu_baseline_md(t, nsample, max_threads=16):
+    """The CPU oracle on the batched MD workload: its deep copy (walk, layout,
+    copy into its own buffer, relocation), one fma pass over every leaf and
+    the copy back, timed together. One thread over the first `nsample`
+    simulations; then every simulation on all the CPUs this process may use
+    (at most max_threads), each thread running the oracle on its own
+    contiguous share of the simulations (they are independent structures).
+    Bytes credited: the GPU step's algorithmic bytes for the same
+    simulations (the oracle moves each leaf byte once per pass: one read, one
+    write)."""
+    import threading
+    import fixtures as fx  # noqa: F401  (the tree is already built)
+    import oracle as orc
+    from paper_1906_01128_amd import dc
+
+    schema = dc.Schema(t.types)
+
+    def step_bytes(roots):
+        p = dc.Plan(schema, t.root_type, roots)
+        b = md_step_bytes(p.info())
+        p.close()
+        return b
+
+    def run(roots, out, k):
+        t0 = time.perf_counter()
+        c = orc.OracleCopy(t.types, t.root_type, roots, 64, 1 << 40)
+        t1 = time.perf_counter()
+        c.run_kernel(1.0001, 0.5, iters=1, select="all")
+        t2 = time.perf_counter()
+        c.copy_back()
+        t3 = time.perf_counter()
+        c.free()
+        out[k] = (t1 - t0, t2 - t1, t3 - t2)
+
+    model, ncpu = host_cpu()
+    roots1 = t.roots[:nsample]
+    r1 = [None]
+    run(roots1, r1, 0)
+    s1 = sum(r1[0])
+    b1 = step_bytes(roots1)
+    nth = max(1, min(ncpu, max_threads))
+    shares = [t.roots[i * len(t.roots) // nth:(i + 1) * len(t.roots) // nth] for i in range(nth)]
+    rn = [None] * nth
+    ths = [threading.Thread(target=run, args=(sh, rn, k)) for k, sh in enumerate(shares)]
+    t0 = time.perf_counter()
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    sn = time.perf_counter() - t0
+    bn = step_bytes(t.roots)
+    return {"value": round(bn / sn / 1e9, 3), "unit": "GB/s", "cores": nth, "kind": "oracle",
+            "sample": f"all {len(t.roots)} simulations, {nth} threads each running the oracle on its own share "
+                      f"(deep copy with relocation + one fma pass + copy back, {sn:.2f} s); credited with the GPU "
+                      f"step's algorithmic bytes ({bn} B)",
+            "cpu_model": model, "cpus_available": ncpu,
+            "single_thread": {"value": round(b1 / s1 / 1e9, 3), "unit": "GB/s", "cores": 1,
+                              "sample": f"first {nsample} simulations, one thread",
+                              "deep_copy_s": round(r1[0][0], 3), "kernel_s": round(r1[0][1], 3),
+                              "copy_back_s": round(r1[0][2], 3), "bytes": b1},
+            "seconds": round(s1 + sn, 2)}
+
+
+def _events(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
 def bench_batched(args, torch, dc):
-    """The batched MD workload: 10,000 simulations, ~7.8 M arrays, ~12 GB.
+    """The batched MD workload: 10,000 simulations, ~7.75 M arrays, ~12 GB.
     Step = one replay of the captured graph that attaches every pointer,
-    runs fma over every leaf and detaches again (one persistent launch or
-    three ordinary ones, whichever the autotuner measured faster)."""
+    runs fma over every leaf and detaches again, in the form and shape the
+    autotuner measured fastest (one persistent launch taking a whole
+    relocation unit per item, one persistent launch in three phases, or
+    three ordinary launches)."""
     import fixtures as fx
     fx.set_threads(0)
     t0 = time.perf_counter()
     t = fx.md()
     log(args, f"md built in {time.perf_counter() - t0:.1f} s")
     ctx = dc.Context(0)
+    schema = dc.Schema(t.types)
     t0 = time.perf_counter()
-    plan = dc.Plan(dc.Schema(t.types), t.root_type, t.roots)
+    plan = dc.Plan(schema, t.root_type, t.roots)
     plan_s = time.perf_counter() - t0
     info = plan.info()
-    log(args, f"planned in {plan_s:.2f} s: {info.nobjects} objects, {info.arena_bytes / 1e9:.2f} GB")
+    log(args, f"planned in {plan_s:.2f} s: {info.nobjects} objects, {info.nsegments} units, "
+              f"{info.arena_bytes / 1e9:.2f} GB, unit leaf runs {info.unit_leaves}")
     arena = torch.empty(plan.arena_bytes, dtype=torch.uint8, device="cuda")
     scratch = torch.empty(plan.scratch_bytes, dtype=torch.uint8, device="cuda")
     s = torch.cuda.current_stream()
@@ -457,101 +561,162 @@ def bench_batched(args, torch, dc):
     tree = dc.Tree(ctx, plan, arena, scratch, relocate=False)
     torch.cuda.synchronize()
     stage_s = time.perf_counter() - t0
-    tune = tree.autotune(reps=2) if args.steps > 2 else None
-    # the autotuner ran the kernel; values drift but the step is the same work
+    tune = tree.autotune(reps=3)
+    table = tree.autotune_results()
+    log(args, f"autotuner: {tune} ({len(table)} candidates)")
+    # the autotuner ran the kernel on the staged image; stage it again so
+    # that the timed steps start from the workload's values
+    tree.release()
+    tree = dc.Tree(ctx, plan, arena, scratch, relocate=False)
     g = tree.graph(a=1.0001, b=0.5, tune=tune)
-    ev = lambda: torch.cuda.Event(enable_timing=True)
-    recs = []
-    for i in range(args.warmup + args.steps):
-        e0, e1 = ev(), ev()
-        e0.record(s)
+    step_bytes = md_step_bytes(info)
+
+    # the timed region: W untimed replays, then exactly K, events around each
+    for _ in range(args.warmup):
         g.launch()
-        e1.record(s)
-        if i >= args.warmup:
-            recs.append((e0, e1))
     torch.cuda.synchronize()
+    ev = _events(torch, 2 * args.steps)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[2 * i].record(s)
+        g.launch()
+        ev[2 * i + 1].record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    step_s = [ev[2 * i].elapsed_time(ev[2 * i + 1]) / 1e3 for i in range(args.steps)]
+    g.close()
     tree.check()
-    step_s = [a.elapsed_time(b) / 1e3 for a, b in recs]
-    # the same work as separate launches: attach, one pass over every leaf, detach
-    phases = {"attach": [], "leaf_tiles": [], "detach": []}
-    tree.attach()   # untimed: builds the tile list of the every-leaf kernel if the graph's differs
-    tree.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.5)
-    tree.detach()
-    for _ in range(3):
-        e = [ev() for _ in range(4)]
-        e[0].record(s)
+    mean_s = sum(step_s) / len(step_s)
+    value = step_bytes / mean_s / 1e9
+
+    form = {0: "one persistent launch, one relocation unit per item" if info.unit_leaves else
+               "one persistent launch in three phases",
+            1: "three launches (relocate, every leaf, reverse relocate)",
+            2: "one persistent launch in three phases"}[tune["launches"]]
+    if tune["launches"] == 1:
+        # the compute launch of the graph, timed as separate launches
+        kname, kbytes = "k_leaf_tiles", 2 * info.leaf_bytes
         tree.attach()
-        e[1].record(s)
-        tree.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.5)
-        e[2].record(s)
+        tree.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.5)  # builds its tile list
+        ks = []
+        for _ in range(5):
+            e = _events(torch, 2)
+            e[0].record(s)
+            tree.run_kernel(mode="resolved", select="all", iters=1, a=1.0001, b=0.5)
+            e[1].record(s)
+            torch.cuda.synchronize()
+            ks.append(e[0].elapsed_time(e[1]) / 1e3)
         tree.detach()
-        e[3].record(s)
+        k_s = sum(ks) / len(ks)
+        k_what = "k_leaf_tiles timed as separate launches beside the graph"
+    else:
+        kname = "k_batch_units" if (tune["launches"] == 0 and info.unit_leaves) else "k_batch"
+        kbytes, k_s = step_bytes, mean_s
+        k_what = (f"{kname} is the whole step: its average launch time is the events' time around each graph "
+                  f"replay (which also holds a one-thread counter reset)")
+    k_ach = kbytes / k_s / 1e9
+    out = {"metric": "deep-copy+kernel effective GB/s vs HBM/link roofline; p50/p99 latency",
+           "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * mean_s, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "batched MD: 10,000 structures sim -> cells U{8..512} -> Poisson(64) atoms -> "
+                                  "pos/vel/force double3 (~12 GB); step = one HIP graph replay of attach + "
+                                  "fma(x, 1.0001, 0.5) over every leaf + detach, image resident in HBM",
+                      "simulations": len(t.roots), "objects": info.nobjects, "slots": info.nslots,
+                      "slots_nonnull": info.nslots_nonnull, "relocation_units": info.nsegments,
+                      "leaf_bytes": info.leaf_bytes, "arena_bytes": plan.arena_bytes, "step_bytes": step_bytes,
+                      "form": form, "tune": tune},
+           "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(k_ach, 1), "peak": HBM_PEAK_GBPS,
+                        "unit": "GB/s", "frac": round(k_ach / HBM_PEAK_GBPS, 4),
+                        "traffic": traffic("batched", kname), "bytes_per_launch": kbytes,
+                        "avg_launch_us": round(1e6 * k_s, 1), "how": k_what},
+           "latency_ms": {"p50": round(1e3 * pct(step_s, 50), 4), "p99": round(1e3 * pct(step_s, 99), 4)},
+           "wall_s": round(wall, 4),
+           "autotuner": [dict(tu, us=round(us, 1)) for tu, us in table],
+           "host": {"plan_s": round(plan_s, 3), "stage_s": round(stage_s, 3)}}
+
+    if not args.no_secondary:
+        out.update(_batched_secondary(args, torch, dc, ctx, t, plan, tree, info, table))
+    if not args.no_link:
+        out["host_link"] = _md_host_link(torch, dc, ctx, plan, arena, scratch, info)
+    tree.release()
+    del arena, scratch
+    torch.cuda.empty_cache()
+    if not args.no_secondary:
+        lin = bench_linear(argparse.Namespace(**dict(vars(args), steps=5, warmup=2)), torch, dc)
+        out["linear_chain"] = {k: lin[k] for k in ("value", "ms_per_step", "config", "roofline", "modes",
+                                                   "mall_flushed", "host_link") if k in lin}
+    if not args.no_cpu_baseline:
+        log(args, "cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline_md(t, nsample=3000)
+    return out
+
+
+def _md_host_link(torch, dc, ctx, plan, arena, scratch, info, reps=3):
+    """The deep copy of the whole MD workload over the host link: pack +
+    host-to-device + attach (dc_deep_copy_to_device), and the copy back of
+    every leaf (device-to-host + scatter into the host tree); medians of
+    `reps` after one untimed round."""
+    peak = link_peak(torch)
+    h2d, d2h = [], []
+    for r in range(1 + reps):
         torch.cuda.synchronize()
-        for k, name in enumerate(("attach", "leaf_tiles", "detach")):
-            phases[name].append(e[k].elapsed_time(e[k + 1]))
-    tree.check()
+        t0 = time.perf_counter()
+        tr = dc.Tree(ctx, plan, arena, scratch)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tr.copy_back()
+        t2 = time.perf_counter()
+        tr.release()
+        if r:
+            h2d.append(plan.arena_bytes / (t1 - t0) / 1e9)
+            d2h.append(info.leaf_bytes / (t2 - t1) / 1e9)
+    a, b = pct(h2d, 50), pct(d2h, 50)
+    return {"what": f"median of {reps}: deep copy (pack + H2D + attach) of the {plan.arena_bytes} B arena, and copy "
+                    f"back of the {info.leaf_bytes} B of leaves (D2H + scatter)",
+            "h2d_GBps": round(a, 2), "d2h_GBps": round(b, 2), "h2d_runs": [round(x, 2) for x in h2d],
+            "d2h_runs": [round(x, 2) for x in d2h],
+            "pinned_peak_h2d_GBps": round(peak["h2d"], 2), "pinned_peak_d2h_GBps": round(peak["d2h"], 2),
+            "spec_peak_GBps": LINK_PEAK_GBPS, "h2d_frac_of_spec": round(a / LINK_PEAK_GBPS, 4),
+            "d2h_frac_of_spec": round(b / LINK_PEAK_GBPS, 4), "h2d_frac_of_measured": round(a / peak["h2d"], 4),
+            "d2h_frac_of_measured": round(b / peak["d2h"], 4)}
+
+
+def _batched_secondary(args, torch, dc, ctx, t, plan, tree, info, table):
+    """Beside the timed step: each batched form's best autotuner time, the
+    MD kick-drift kernel and the first 500 simulations one structure per
+    call against one graph replay."""
+    s = torch.cuda.current_stream()
+    step_bytes = md_step_bytes(info)
+    best = {}
+    for tu, us in table:
+        key = {0: "persistent_units" if info.unit_leaves else "persistent_phased", 1: "three_launches",
+               2: "persistent_phased"}[tu["launches"]]
+        if key not in best or us < best[key]["us"]:
+            best[key] = dict(tu, us=round(us, 1), GBps=round(step_bytes / us / 1e3, 1))
     # the MD kick-drift kernel on the same cells: v += f dt/m, x += v dt
     tree.attach()
     dt = 1e-3
     tree.kick_drift(1, 0, 1, 2, dt, dt / 39.948, steps=1)   # builds the element list
     kd = []
     for _ in range(5):
-        e0, e1 = ev(), ev()
-        e0.record(s)
+        e = _events(torch, 2)
+        e[0].record(s)
         tree.kick_drift(1, 0, 1, 2, dt, dt / 39.948, steps=1)
-        e1.record(s)
+        e[1].record(s)
         torch.cuda.synchronize()
-        kd.append(e0.elapsed_time(e1) / 1e3)
+        kd.append(e[0].elapsed_time(e[1]) / 1e3)
     tree.check()
     tree.detach()
-    # the same step as one persistent launch, in its best measured shape, for
-    # comparison when the autotuner picked three launches (last: it rebuilds
-    # the tile list for its own tile size)
-    pt = dict(block=1024, wg_per_cu=2, tile_chunks=16384, launches=0)
-    tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=pt)
-    pers = []
-    for _ in range(3):
-        e0, e1 = ev(), ev()
-        e0.record(s)
-        tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=pt)
-        e1.record(s)
-        torch.cuda.synchronize()
-        pers.append(e0.elapsed_time(e1) / 1e3)
-    tree.check()
     kd_bytes = 40 * (info.leaf_bytes // 24)    # per double of x: read x, v, f; write x, v
     kd_gbps = kd_bytes / pct(kd, 50) / 1e9
-    plain = _batched_vs_plain(torch, dc, ctx, t, tune, nsub=500)
-    kb = 2 * info.leaf_bytes
-    rb = 2 * (info.nslots_nonnull * 16 + info.nslots * 8 + info.nobjects * 16)
-    v = (kb + rb) / pct(step_s, 50) / 1e9
-    kname = "k_leaf_tiles" if (tune or {"launches": 1}).get("launches") else "k_batch"
-    if kname == "k_leaf_tiles":   # the compute launch of the graph, timed as a separate launch
-        k_s = pct(phases["leaf_tiles"], 50) / 1e3
-        k_ach = kb / k_s / 1e9
-    else:                         # one persistent launch does the whole step
-        k_s = pct(step_s, 50)
-        k_ach = v
-    return {"metric": "deep-copy+kernel effective GB/s vs HBM/link roofline; p50/p99 latency",
-            "value": round(v, 2), "unit": "GB/s", "ms_per_step": round(1e3 * pct(step_s, 50), 3),
-            "steps": args.steps, "dtype": "f64",
-            "config": {"workload": "batched MD: 10,000 sims -> cells U{8..512} -> Poisson(64) atoms -> "
-                                   "pos/vel/force double3; attach + fma over every leaf + detach per graph replay "
-                                   "(one persistent launch or three launches, as the autotuner picks)",
-                       "objects": info.nobjects, "slots": info.nslots_nonnull, "leaf_bytes": info.leaf_bytes,
-                       "arena_bytes": plan.arena_bytes, "tune": tune},
-            "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(k_ach, 1), "peak": HBM_PEAK_GBPS,
-                         "unit": "GB/s", "frac": round(k_ach / HBM_PEAK_GBPS, 4), "traffic": traffic("batched", kname),
-                         "avg_launch_us": round(1e6 * k_s, 1)},
-            "latency_ms": {"p50": round(1e3 * pct(step_s, 50), 3), "p99": round(1e3 * pct(step_s, 99), 3)},
-            "separate_launches_ms": {k: round(pct(v_, 50), 3) for k, v_ in phases.items()},
-            "persistent_launch": {"tune": pt, "ms": round(1e3 * pct(pers, 50), 3),
-                                  "over_step": round(pct(pers, 50) / pct(step_s, 50), 3)},
-            "one_structure_per_call": plain,
+    plain = _batched_vs_plain(torch, dc, ctx, t, None, nsub=500)
+    return {"forms": best,
             "kick_drift": {"kernel": "k_kick_drift", "ms": round(1e3 * pct(kd, 50), 3),
                            "bytes_per_launch": kd_bytes, "achieved_GBps": round(kd_gbps, 1),
                            "frac": round(kd_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic("batched", "k_kick_drift")},
-            "host": {"plan_s": round(plan_s, 3), "stage_s": round(stage_s, 3),
-                     "stage_GBps": round(plan.arena_bytes / stage_s / 1e9, 2)}}
+            "one_structure_per_call": plain}
 
 
 def _served_run(dc, ctx, schema, pool, sizes, jobs, outs, lam, budget):

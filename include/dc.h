@@ -123,6 +123,10 @@ typedef struct {
   uint64_t out_bytes;     /* out-of-place leaf image size (see dc_kernel_args) */
   uint64_t nsegments;     /* relocation work units */
   uint64_t nroots;
+  uint64_t unit_leaves;   /* 1: every relocation unit's slots first reach one
+                             contiguous run of leaves, so the persistent batched
+                             launch takes a whole unit per item (dc_batch_run) */
+  uint64_t max_unit_leaf_bytes; /* the largest such run, in 16-byte chunks x 16 */
 } dc_plan_info;
 
 /* ---- lifecycle --------------------------------------------------------------- */
@@ -384,25 +388,34 @@ typedef struct {
                               512..2^20 (DC_E_INVAL otherwise) */
   uint32_t launches;       /* 0: one persistent launch; 1: three ordinary launches
                               (relocate, every leaf, reverse relocate), for which
-                              block and wg_per_cu are not used */
+                              block and wg_per_cu are not used; 2: one persistent
+                              launch in three phases (what 0 runs when the plan's
+                              relocation units do not own contiguous leaf runs) */
   uint32_t spin_limit;     /* persistent launch: polls (about 1 us each) a workgroup
                               waits for a phase to finish before it records an error
                               and goes on, so that every launch ends; 0: 2^24 */
 } dc_tune;
 
-/* DC_BATCH_FORCE_WAIT_BOUND is for tests of the error path only: every wait
- * of the persistent launch waits for one item more than its phase has, so
- * each wait ends at its bound (keep tune->spin_limit small); the launch still
- * ends, the tree's leaf values and slots are then unspecified, and the next
- * check of the tree returns DC_E_STATE. DC_E_INVAL with three launches. */
+/* DC_BATCH_FORCE_WAIT_BOUND is for tests of the error path only: it runs the
+ * three-phase persistent launch, in which every wait waits for one item more
+ * than its phase has, so each wait ends at its bound (keep tune->spin_limit
+ * small); the launch still ends, the tree's leaf values and slots are then
+ * unspecified, and the next check of the tree returns DC_E_STATE. DC_E_INVAL
+ * with three launches. */
 enum { DC_BATCH_ATTACH = 1, DC_BATCH_DETACH = 2, DC_BATCH_FORCE_WAIT_BOUND = 4 };
 /* Every structure's relocation and its leaves' kernel (args: RESOLVED,
- * ALL_LEAVES, iters == 1). tune->launches 0: one persistent launch whose
- * workgroups take relocation units, then compute tiles, then (DETACH)
- * reverse relocation units from one device work queue; 1: the same work as
- * three stream-ordered launches. ATTACH requires a staged (unrelocated)
- * tree; DETACH leaves it staged again. tune NULL: the cached autotuner choice
- * or defaults. Asynchronous on `stream`. */
+ * ALL_LEAVES, iters == 1), the batched use of Figure 2(d) and Algorithm 2
+ * step 4. tune->launches 0: one persistent launch whose workgroups take items
+ * from one device work queue. When every relocation unit's slots first reach
+ * one contiguous run of leaves (depth-first layouts whose structs list leaf
+ * members before deeper struct members), an item is a whole unit: its attach,
+ * the kernel over its leaves (addresses read from the slots it just wrote)
+ * and its detach, with no wait between workgroups. Otherwise the launch runs
+ * in three phases: attach units, then compute tiles, then (DETACH) reverse
+ * relocation units, each phase waiting for the one before. 2: always the
+ * three phases. 1: the same work as three stream-ordered launches. ATTACH
+ * requires a staged (unrelocated) tree; DETACH leaves it staged again. tune
+ * NULL: the cached autotuner choice or defaults. Asynchronous on `stream`. */
 dc_status dc_batch_run(dc_tree tree, const dc_kernel_args* args, const dc_tune* tune, uint32_t flags, void* stream);
 
 /* Times candidate tile shapes of dc_batch_run with ATTACH|DETACH on this
@@ -414,6 +427,11 @@ dc_status dc_batch_run(dc_tree tree, const dc_kernel_args* args, const dc_tune* 
  * attached or a device check fails; DC_E_RANGE for a d_out too small or
  * misaligned; DC_E_HIP. */
 dc_status dc_autotune(dc_tree tree, const dc_kernel_args* args, uint32_t reps, dc_tune* out);
+/* The candidates the tree's last dc_autotune timed, in order, with the median
+ * time of each in microseconds: up to `cap` of them into tunes[] and us[]
+ * (caller-owned), their number in *n (0 before any autotune). Errors:
+ * DC_E_INVAL for a NULL or released tree, NULL n, or NULL arrays with cap > 0. */
+dc_status dc_autotune_results(dc_tree tree, dc_tune* tunes, double* us, uint32_t cap, uint32_t* n);
 
 /* Captures dc_batch_run(tree, args, tune, flags) into a HIP graph; optionally
  * preceded by the host-to-device transfer of the staged image (upload != 0,

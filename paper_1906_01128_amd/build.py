@@ -24,8 +24,19 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-ta
          "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def _compile(src, obj, verbose):
-    cmd = [HIPCC, "-x", "hip", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def build_id():
+    """Hash of the library sources: the autotuner keys its cached choices by it."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)) + ["../../include/dc.h"]:
+        path = os.path.normpath(os.path.join(CSRC, name))
+        if os.path.isfile(path):
+            h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src, obj, verbose, bid):
+    cmd = [HIPCC, "-x", "hip", *FLAGS, f'-DDC_BUILD_ID="{bid}"', "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,8 +55,9 @@ def build(verbose=False):
     os.makedirs(objdir, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o") for s in srcs]
+    bid = build_id()
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(srcs, objs)))
+        list(ex.map(lambda so: _compile(so[0], so[1], verbose, bid), zip(srcs, objs)))
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)

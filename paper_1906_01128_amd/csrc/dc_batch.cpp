@@ -14,11 +14,15 @@
 
 namespace dc {
 
+#ifndef DC_BUILD_ID
+#define DC_BUILD_ID "unversioned"
+#endif
+
 static const dc_tune kDefaultTune = {256, 4, 1024, 1, 0};
 static const uint32_t kDefaultSpin = 1u << 24;  // polls of a persistent workgroup's wait
 
 static dc_status check_tune(const dc_tune& t) {
-  if (t.launches > 1) return fail(DC_E_INVAL, "tune.launches %u (0 or 1)", t.launches);
+  if (t.launches > 2) return fail(DC_E_INVAL, "tune.launches %u (0, 1 or 2)", t.launches);
   if (t.block != 256 && t.block != 512 && t.block != 1024) return fail(DC_E_INVAL, "tune.block %u", t.block);
   if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return fail(DC_E_INVAL, "tune.wg_per_cu %u", t.wg_per_cu);
   if (t.tile_chunks < kTileMinChunks || t.tile_chunks > kTileMaxChunks || (t.tile_chunks & (t.tile_chunks - 1)))
@@ -52,8 +56,10 @@ static std::string tune_key(dc_tree t) {
   (void)hipGetDevice(&dev);
   hipDeviceProp_t prop;
   const char* arch = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.gcnArchName : "unknown";
-  snprintf(buf, sizeof(buf), "%s/cu%d/seg%d/leaf%d/chunk%d", arch, t->ctx->ncu, bucket(p->segs.size()),
-           bucket(p->leaves.size()), bucket(p->total_chunks));
+  // the library build is part of the key: a choice measured with other
+  // kernels is not reused
+  snprintf(buf, sizeof(buf), "%s/%s/cu%d/seg%d/leaf%d/chunk%d/u%d", DC_BUILD_ID, arch, t->ctx->ncu,
+           bucket(p->segs.size()), bucket(p->leaves.size()), bucket(p->total_chunks), p->unit_leaves ? 1 : 0);
   return buf;
 }
 
@@ -115,24 +121,38 @@ static dc_status resolve_tune(dc_tree t, const dc_tune* tune, dc_tune* out) {
   return check_tune(*out);
 }
 
-// enqueue the persistent launch (and its counter reset) on s; under graph
-// capture the tile index must already be built and complete
+// the persistent launch takes one relocation unit with its leaves per item
+// when the plan's units own contiguous leaf runs (and no wait is to be forced)
+static bool unit_items(dc_tree t, const dc_tune& tu, uint32_t flags) {
+  return tu.launches == 0 && t->plan->unit_leaves && !(flags & DC_BATCH_FORCE_WAIT_BOUND);
+}
+
+// whether the chosen form reads the tile list
+static bool uses_tiles(dc_tree t, const dc_tune& tu, uint32_t flags) {
+  return !t->plan->leaves.empty() && !unit_items(t, tu, flags);
+}
+
+// enqueue the chosen form on s (the persistent launches after their counter
+// reset); under graph capture the tile index must already be built and complete
 static dc_status enqueue_batch(dc_tree t, const LeafArgs& la, const dc_tune& tu, uint32_t flags, hipStream_t s,
                                bool capturing = false) {
   dc_plan p = t->plan;
-  if (!p->leaves.empty() && !capturing) DC_TRY(tree_ensure_tiles(t, tu.tile_chunks, s));
+  if (uses_tiles(t, tu, flags) && !capturing) DC_TRY(tree_ensure_tiles(t, tu.tile_chunks, s));
   const uint64_t ntiles = p->leaves.empty() ? 0 : t->ntiles;
+  const uint32_t grid = (uint32_t)t->ctx->ncu * tu.wg_per_cu;
   hipError_t e = hipSuccess;
   if (tu.launches == 1) {
     // the same work as three ordinary launches: relocate, every leaf, reverse
     if (flags & DC_BATCH_ATTACH) e = launch_relocate(t->tab, true, s);
     if (e == hipSuccess) e = launch_leaf_tiles(t->tab, la, ntiles, t->tile_T, false, s);
     if (e == hipSuccess && (flags & DC_BATCH_DETACH)) e = launch_relocate(t->tab, false, s);
+  } else if (unit_items(t, tu, flags)) {
+    e = launch_reset_counters(t->tab.hdr, s);
+    if (e == hipSuccess) e = launch_batch_units(t->tab, la, flags, tu.block, grid, s);
   } else {
     e = launch_reset_counters(t->tab.hdr, s);
     if (e == hipSuccess)
-      e = launch_batch(t->tab, la, flags, tu.block, (uint32_t)t->ctx->ncu * tu.wg_per_cu, ntiles,
-                       tu.spin_limit ? tu.spin_limit : kDefaultSpin, s);
+      e = launch_batch(t->tab, la, flags, tu.block, grid, ntiles, tu.spin_limit ? tu.spin_limit : kDefaultSpin, s);
   }
   if (e != hipSuccess) return fail(DC_E_HIP, "batch launch: %s", hipGetErrorString(e));
   return DC_OK;
@@ -168,8 +188,8 @@ dc_status dc_batch_run(dc_tree t, const dc_kernel_args* a, const dc_tune* tune, 
   DC_TRY(batch_args(t, a, &la));
   dc_tune tu;
   DC_TRY(resolve_tune(t, tune, &tu));
-  if ((flags & DC_BATCH_FORCE_WAIT_BOUND) && tu.launches != 0)
-    return fail(DC_E_INVAL, "FORCE_WAIT_BOUND needs the persistent launch (tune.launches 0)");
+  if ((flags & DC_BATCH_FORCE_WAIT_BOUND) && tu.launches == 1)
+    return fail(DC_E_INVAL, "FORCE_WAIT_BOUND needs a persistent launch (tune.launches 0 or 2)");
   DC_HIP(hipSetDevice(t->ctx->device));
   DC_TRY(enqueue_batch(t, la, tu, flags, (hipStream_t)stream));
   if (flags & DC_BATCH_DETACH) t->attached = false;
@@ -190,15 +210,22 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
   DC_HIP(hipEventCreate(&e0));
   DC_HIP(hipEventCreate(&e1));
   const uint32_t flags = DC_BATCH_ATTACH | DC_BATCH_DETACH;
+  // Candidates: persistent shapes whose workgroups are all resident at once
+  // (at most 2048 threads per compute unit), the per-unit form when the plan
+  // allows it, the three-phase form over several tile sizes, and three
+  // ordinary launches over several tile sizes.
   std::vector<dc_tune> cands;
-  for (uint32_t block : {256u, 512u})
-    for (uint32_t tile : {1024u, 4096u, 16384u})
-      for (uint32_t wg : {2u, 4u, 8u}) {
-        dc_tune c{block, wg, tile, 0, 0};
-        if (check_tune(c) == DC_OK) cands.push_back(c);
-      }
+  const uint32_t phased = t->plan->unit_leaves ? 2u : 0u;
+  for (uint32_t block : {256u, 512u, 1024u})
+    for (uint32_t wg : {1u, 2u, 4u, 8u}) {
+      if (block * wg > 2048 || block * wg < 512) continue;
+      if (t->plan->unit_leaves) cands.push_back(dc_tune{block, wg, kDefaultTune.tile_chunks, 0, 0});
+      for (uint32_t tile : {4096u, 16384u})
+        if (block * wg >= 1024) cands.push_back(dc_tune{block, wg, tile, phased, 0});
+    }
   for (uint32_t tile : {512u, 1024u, 2048u, 4096u}) cands.push_back(dc_tune{256, 1, tile, 1, 0});
   clear_error();
+  t->tune_table.clear();
   dc_tune best = kDefaultTune;
   double best_us = 1e300;
   dc_status st = DC_OK;
@@ -218,6 +245,7 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
     if (st != DC_OK) break;
     std::sort(ms.begin(), ms.end());
     const double us = 1000.0 * ms[ms.size() / 2];
+    t->tune_table.push_back({c, us});
     if (us < best_us) {
       best_us = us;
       best = c;
@@ -231,6 +259,17 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
   DC_TRY(tree_check(t, nullptr));
   cache_store(tune_key(t), best, best_us);
   *out = best;
+  return DC_OK;
+}
+
+dc_status dc_autotune_results(dc_tree t, dc_tune* tunes, double* us, uint32_t cap, uint32_t* n) {
+  if (!t || t->released || !n || (cap && (!tunes || !us))) return fail(DC_E_INVAL, "dc_autotune_results: null argument");
+  const uint32_t m = (uint32_t)std::min<size_t>(cap, t->tune_table.size());
+  for (uint32_t i = 0; i < m; i++) {
+    tunes[i] = t->tune_table[i].first;
+    us[i] = t->tune_table[i].second;
+  }
+  *n = (uint32_t)t->tune_table.size();
   return DC_OK;
 }
 
@@ -257,7 +296,7 @@ dc_status dc_graph_create(dc_tree t, const dc_kernel_args* a, const dc_tune* tun
   hipStream_t cs;
   DC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   // the tile index is built outside the graph; the graph only replays the launch
-  if (!p->leaves.empty()) {
+  if (uses_tiles(t, tu, flags)) {
     dc_status st = tree_ensure_tiles(t, tu.tile_chunks, cs);
     if (st != DC_OK) return cleanup(st);
     g->tile_T = tu.tile_chunks;

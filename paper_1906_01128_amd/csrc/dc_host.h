@@ -149,6 +149,7 @@ struct Obj {
   uint32_t parent;      // first discoverer, kNone for a root
   uint32_t sobj;        // index among slotted struct arrays, kNone otherwise
   uint64_t parent_rel;  // offset of the discovering slot inside the parent
+  uint64_t slot;        // index of the discovering slot in the slot enumeration (roots: ~0)
   uint32_t depth;       // pointer hops from the root
   uint32_t pad;
 };
@@ -188,6 +189,11 @@ struct dc_plan_s {
   std::vector<uint32_t> leaves;
   std::vector<uint64_t> leaf_pre, leaf_info, leaf_slot, leaf_out;
   uint64_t out_bytes = 0, total_chunks = 0, total_hops = 0;
+  // every relocation unit's slots discover a contiguous run of leaves (in
+  // leaf order), recorded in its DevSeg: the persistent launch can then run
+  // each unit's attach, its leaves and its detach as one work item
+  bool unit_leaves = false;
+  uint64_t max_unit_leaf_chunks = 0;
   dc::ScratchLayout sl{};
   uint64_t arena_bytes = 0, payload_bytes = 0, leaf_bytes = 0, nslots_nonnull = 0;
 };
@@ -209,6 +215,7 @@ struct dc_tree_s {
   uint64_t ntiles = 0;
   hipEvent_t tiles_ev = nullptr;    // recorded after the tile index was built
   dc::KdTables* kd = nullptr;       // element list of the kick-drift kernel (device)
+  std::vector<std::pair<dc_tune, double>> tune_table;  // the last autotune: shape, median us
 };
 
 namespace dc {

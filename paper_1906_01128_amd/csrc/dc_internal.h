@@ -71,7 +71,9 @@ struct DevSeg {
   uint64_t slot_lo, slot_hi;  // slot range [lo, hi)
   uint64_t tgt_lo, tgt_hi;    // range in the target table
   uint32_t sobj_lo, sobj_hi;  // struct objects overlapping the slot range
-  uint32_t pad[2];
+  // leaves [leaf_lo, leaf_hi) (leaf order) whose discovering slot lies in the
+  // range; meaningful when every unit's leaves are contiguous (the plan says so)
+  uint32_t leaf_lo, leaf_hi;
 };
 
 // Leaf (FP32/FP64 array with >= 1 element) records for the compute kernels.
@@ -231,6 +233,10 @@ hipError_t launch_stream_deref(const Tables& t, const HopArgs& h, uint64_t count
 // spin_limit: polls of a workgroup's wait for a phase before it records kErrSpin
 hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
                         uint64_t ntiles, uint32_t spin_limit, hipStream_t s);
+// one persistent launch, one queue item per relocation unit (attach, the
+// unit's contiguous leaves, detach); needs the plan's per-unit leaf runs
+hipError_t launch_batch_units(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
+                              hipStream_t s);
 hipError_t launch_reset_counters(DevHeader* hdr, hipStream_t s);
 int device_cu_count();
 

@@ -122,11 +122,18 @@ __device__ __noinline__ void report_wild(DevHeader* hdr) {
 // value that is not one of the unit's planned targets is left alone and
 // reported in the header. Three dependent rounds of global accesses: the
 // unit's tables; the slots' current values together with the targets'
-// translations; the translated stores. Needs at least 256 threads: a unit's
-// at most 1024 slots are four per thread.
+// translations; the translated stores. A unit's at most 1024 slots are KS per
+// thread: four for 256 threads, two for 512, one for 1024.
 static_assert(kSegMaxSlots <= 4 * 256, "four slots per thread of a 256-thread workgroup");
 
-__device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t* lds) {
+// A slot the unit translated, kept by a caller that restores it later: its
+// arena offset (kKeepBad set when its value was not a planned target, ~0 for
+// none) and its value before the translation.
+constexpr uint64_t kKeepBad = 1ull << 63;
+
+template <bool KEEP, int KS = 4>
+__device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t* lds, uint64_t* keep_off = nullptr,
+                              uint64_t* keep_val = nullptr) {
   RelocLds* L = (RelocLds*)lds;
   RelocType* types = (RelocType*)(lds + sizeof(RelocLds));
   const int tid = threadIdx.x, bs = blockDim.x;
@@ -157,11 +164,12 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
   }
   lds_barrier();
 
-  // the thread's slots (at most four): their arena offsets and current values
-  uint64_t soff[4], val[4];
-  bool fol[4];
+  // the thread's slots (at most KS, with bs * KS >= kSegMaxSlots): their
+  // arena offsets and current values
+  uint64_t soff[KS], val[KS];
+  bool fol[KS];
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
+  for (int k = 0; k < KS; k++) {
     const uint32_t jr = (uint32_t)k * bs + tid;  // slot - first slot
     soff[k] = ~0ull;
     val[k] = 0;
@@ -193,7 +201,8 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
   lds_barrier();
 
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
+  for (int k = 0; k < KS; k++) {
+    if (KEEP) keep_off[k] = ~0ull;
     if (soff[k] == ~0ull || val[k] == 0) continue;
     // a member left out of a selective copy reads as null on the device
     if (!fol[k]) {
@@ -203,16 +212,21 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
     uint64_t nv;
     if (!hash_find(L->keys, L->vals, val[k], &nv)) {
       report_bad_slot(t.hdr, soff[k]);
+      if (KEEP) keep_off[k] = soff[k] | kKeepBad;
       continue;
     }
     *(g_u64*)(B + soff[k]) = nv;
+    if (KEEP) {
+      keep_off[k] = soff[k];
+      keep_val[k] = val[k];
+    }
   }
 }
 
 __global__ void __launch_bounds__(kRelocBlock, 8) k_relocate(Tables t, int attach) {
   extern __shared__ __align__(16) uint8_t lds[];
   for (uint64_t sg = blockIdx.x; sg < t.nseg; sg += gridDim.x) {
-    relocate_unit(t, sg, attach != 0, lds);
+    relocate_unit<false>(t, sg, attach != 0, lds);
     lds_barrier();
   }
 }
@@ -783,7 +797,7 @@ __global__ void __launch_bounds__(BS, 8) k_batch(Tables t, LeafArgs la, uint32_t
     }
     if (item >= total) break;
     if (item < nA) {
-      relocate_unit(t, item, true, lds);
+      relocate_unit<false>(t, item, true, lds);
       lds_barrier();
       myA++;
     } else if (item < nA + nB) {
@@ -797,9 +811,125 @@ __global__ void __launch_bounds__(BS, 8) k_batch(Tables t, LeafArgs la, uint32_t
         wait_count(hdr, &hdr->doneB, nB + extra, spin_limit);
         waitedB = true;
       }
-      relocate_unit(t, item - nA - nB, false, lds);
+      relocate_unit<false>(t, item - nA - nB, false, lds);
       lds_barrier();
     }
+  }
+}
+
+// ---- persistent relocate + compute, one item per relocation unit ---------------------------
+//
+// When every relocation unit's slots are the first to reach one contiguous run
+// of leaves (the plan records the run in the unit), a unit's attach, the
+// kernel over its leaves and its detach depend on nothing another unit does:
+// the leaves' addresses are read from slots of that unit alone, and its
+// detach rewrites slots that only its own leaves were reached through. One
+// workgroup then takes a whole unit as one item of the device queue, with
+// workgroup-scope ordering only, and no workgroup ever waits for another.
+// With ATTACH and DETACH both, the detach writes back the slot values the
+// attach read, held in registers; alone, it translates through the unit's
+// LDS table as the separate reverse relocation does.
+
+// Every chunk of leaves [l0, l1) (at most kTileMaxLeaves of them), in rounds
+// of U chunks per thread; each leaf's address is read once from its relocated
+// parent slot. Ends with an LDS barrier: the next run may overwrite the tables.
+template <int U>
+__device__ void leaf_run(const Tables& t, const LeafArgs& la, uint32_t l0, uint32_t l1, uint8_t* lds) {
+  constexpr uint32_t N = kTileMaxLeaves + 2;
+  uint64_t* pre = (uint64_t*)lds;
+  uint64_t* addr = pre + N;
+  uint64_t* info = addr + N;
+  uint64_t* outo = info + N;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const uint32_t nl = l1 - l0;
+  for (uint32_t i = tid; i <= nl; i += bs) {
+    const uint32_t l = l0 + i;
+    pre[i] = t.leaf_pre[l];
+    if (i == nl) continue;
+    const uint64_t inf = t.leaf_info[l];
+    info[i] = inf;
+    outo[i] = t.leaf_out[l];
+    const uint64_t a = *(const g_u64*)((uint64_t)t.arena + t.leaf_slot[l]);
+    if (in_arena(t, a, inf & ((1ull << kLeafKindShift) - 1))) {
+      addr[i] = a;
+    } else {
+      addr[i] = 0;
+      report_wild(t.hdr);
+    }
+  }
+  lds_barrier();
+  const uint64_t c_end = pre[nl];
+  for (uint64_t c_lo = pre[0]; c_lo < c_end; c_lo += (uint64_t)bs * U) {
+    Vec16 v[U];
+    uint64_t src[U], dst[U];
+    uint32_t nb[U];
+    bool f64[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+      const uint64_t c = c_lo + (uint64_t)k * bs + tid;
+      nb[k] = 0;
+      f64[k] = false;
+      src[k] = dst[k] = 0;
+      if (c < c_end) {
+        const uint32_t i = find_leaf(pre, nl, c);
+        const uint64_t byte = (c - pre[i]) * kChunk;
+        const uint64_t lb = info[i] & ((1ull << kLeafKindShift) - 1);
+        f64[k] = (info[i] >> kLeafKindShift) == DC_KIND_F64;
+        nb[k] = addr[i] == 0 ? 0 : (uint32_t)(lb - byte < kChunk ? lb - byte : kChunk);
+        src[k] = (la.src_out ? (uint64_t)la.out + outo[i] : addr[i]) + byte;
+        dst[k] = (la.out ? (uint64_t)la.out + outo[i] : addr[i]) + byte;
+      }
+      if (nb[k] == kChunk) v[k].u = gload16(src[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+      if (nb[k] == kChunk) {
+        fma_chunk_any(v[k], f64[k], la);
+        gstore16(dst[k], v[k].u);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; k++)
+      if (nb[k] != 0 && nb[k] != kChunk) fma_partial(src[k], dst[k], nb[k], f64[k] ? DC_KIND_F64 : DC_KIND_F32, la);
+  }
+  lds_barrier();
+}
+
+template <int U, int BS>
+__global__ void __launch_bounds__(BS, 8) k_batch_units(Tables t, LeafArgs la, uint32_t flags) {
+  constexpr int KS = (int)((kSegMaxSlots + BS - 1) / BS);
+  extern __shared__ __align__(16) uint8_t lds[];
+  __shared__ uint32_t s_item;
+  const bool att = (flags & DC_BATCH_ATTACH) != 0, det = (flags & DC_BATCH_DETACH) != 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&t.hdr->queue, 1u);
+    lds_barrier();
+    const uint32_t u = s_item;
+    lds_barrier();
+    if (u >= t.nseg) break;
+    uint64_t koff[KS], kval[KS];
+    if (att) {
+      relocate_unit<true, KS>(t, u, true, lds, koff, kval);
+      // the translated slots (global stores of other threads) are read below
+      __syncthreads();
+    }
+    const uint32_t lhi = t.segs[u].leaf_hi;
+    for (uint32_t l = t.segs[u].leaf_lo; l < lhi; l += kTileMaxLeaves)
+      leaf_run<U>(t, la, l, l + kTileMaxLeaves < lhi ? l + kTileMaxLeaves : lhi, lds);
+    if (det) {
+      if (att) {
+        // every read of these slots completed before the last run's barrier
+#pragma unroll
+        for (int k = 0; k < KS; k++) {
+          if (koff[k] == ~0ull) continue;
+          if (koff[k] & kKeepBad) report_bad_slot(t.hdr, koff[k] & ~kKeepBad);
+          else *(g_u64*)((uint64_t)t.arena + koff[k]) = kval[k];
+        }
+      } else {
+        relocate_unit<false, KS>(t, u, false, lds);
+      }
+    }
+    lds_barrier();
   }
 }
 
@@ -931,6 +1061,27 @@ hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uin
       break;
     case 1024:
       hipLaunchKernelGGL((k_batch<1, 1024>), dim3(grid), dim3(block), lds, s, t, la, flags, ntiles, per_item, spin_limit);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_units(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
+                              hipStream_t s) {
+  if (t.ntypes > kMaxTypes) return hipErrorInvalidValue;
+  const size_t rl = reloc_lds_bytes(t.ntypes);
+  const size_t lds = kTileLds > rl ? kTileLds : rl;
+  switch (block) {
+    case 256:
+      hipLaunchKernelGGL((k_batch_units<2, 256>), dim3(grid), dim3(block), lds, s, t, la, flags);
+      break;
+    case 512:
+      hipLaunchKernelGGL((k_batch_units<2, 512>), dim3(grid), dim3(block), lds, s, t, la, flags);
+      break;
+    case 1024:
+      hipLaunchKernelGGL((k_batch_units<1, 1024>), dim3(grid), dim3(block), lds, s, t, la, flags);
       break;
     default:
       return hipErrorInvalidValue;

@@ -99,7 +99,7 @@ struct Walker {
   uint64_t nslots = 0;
 
   dc_status emit(uint64_t host, uint32_t kind, uint32_t type, uint64_t count, uint32_t parent, uint64_t rel,
-                 uint32_t* out) {
+                 uint64_t slot, uint32_t* out) {
     if (p->objs.size() >= kNone - 1) return fail(DC_E_RANGE, "more than 2^32-2 objects");
     Obj o{};
     o.host = host;
@@ -109,6 +109,7 @@ struct Walker {
     o.bytes = count * elem_size(p->types, kind, type);
     o.parent = parent;
     o.parent_rel = rel;
+    o.slot = slot;
     o.depth = parent == kNone ? 0 : p->objs[parent].depth + 1;
     o.sobj = kNone;
     const uint32_t idx = (uint32_t)p->objs.size();
@@ -147,7 +148,7 @@ struct Walker {
       p->root_obj.push_back(idx);
       return DC_OK;
     }
-    DC_TRY(emit(root, DC_KIND_STRUCT, p->root_type, 1, kNone, 0, &idx));
+    DC_TRY(emit(root, DC_KIND_STRUCT, p->root_type, 1, kNone, 0, ~0ull, &idx));
     p->root_obj.push_back(idx);
     std::vector<Frame> stack;
     if (p->objs[idx].sobj != kNone) stack.push_back({idx, 0, 0});
@@ -189,7 +190,7 @@ struct Walker {
         continue;
       }
       uint32_t child;
-      DC_TRY(emit(ptr, fd.kind, ptype, count, from, rel, &child));
+      DC_TRY(emit(ptr, fd.kind, ptype, count, from, rel, slot, &child));
       p->slot_target[slot] = child;
       p->nslots_nonnull++;
       if (p->objs[child].sobj != kNone) stack.push_back({child, 0, 0});
@@ -355,6 +356,35 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     p->out_bytes = first ? 0 : align_up(oend, align);
   }
 
+  // the leaves each relocation unit's slots discover: a leaf belongs to the
+  // unit holding the slot that first reached it. When the owning units never
+  // decrease along the leaf order (a depth-first layout whose struct arrays
+  // list their leaf members before deeper struct members, as every workload
+  // here does), every unit owns one contiguous run of leaves
+  {
+    const uint64_t nl = p->leaves.size(), ns = p->segs.size();
+    bool mono = ns > 0 && ns < kNone;
+    uint64_t u = 0;
+    for (uint64_t s = 0; s < ns; s++) p->segs[s].leaf_lo = p->segs[s].leaf_hi = 0;
+    for (uint64_t l = 0; l < nl && mono; l++) {
+      const uint64_t slot = p->objs[p->leaves[l]].slot;
+      while (u + 1 < ns && p->segs[u].slot_hi <= slot) u++;
+      if (slot < p->segs[u].slot_lo || slot >= p->segs[u].slot_hi) mono = false;  // an earlier unit
+      else if (p->segs[u].leaf_hi == 0) p->segs[u].leaf_lo = (uint32_t)l, p->segs[u].leaf_hi = (uint32_t)l + 1;
+      else p->segs[u].leaf_hi = (uint32_t)l + 1;
+    }
+    // units without leaves get the empty run where the next leaves start
+    uint32_t at = (uint32_t)nl;
+    for (uint64_t s = ns; s-- > 0;) {
+      if (p->segs[s].leaf_hi == 0) p->segs[s].leaf_lo = p->segs[s].leaf_hi = at;
+      else at = p->segs[s].leaf_lo;
+    }
+    p->unit_leaves = mono && nl > 0 && nl < kNone;
+    for (uint64_t s = 0; s < ns && p->unit_leaves; s++)
+      p->max_unit_leaf_chunks = std::max<uint64_t>(
+          p->max_unit_leaf_chunks, p->leaf_pre[p->segs[s].leaf_hi] - p->leaf_pre[p->segs[s].leaf_lo]);
+  }
+
   // device types
   p->dev_types.resize(p->types.size());
   for (size_t i = 0; i < p->types.size(); i++) {
@@ -462,6 +492,8 @@ dc_status dc_plan_query(dc_plan p, dc_plan_info* out) {
   out->out_bytes = p->out_bytes;
   out->nsegments = p->segs.size();
   out->nroots = p->roots.size();
+  out->unit_leaves = p->unit_leaves ? 1 : 0;
+  out->max_unit_leaf_bytes = p->max_unit_leaf_chunks * kChunk;
   return DC_OK;
 }
 

@@ -70,7 +70,8 @@ OBJECT_DTYPE = np.dtype([("host", "<u8"), ("off", "<u8"), ("bytes", "<u8"), ("co
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, u64) for n in ("nobjects", "nslots", "nslots_nonnull", "nleaves", "payload_bytes", "leaf_bytes",
-                                   "arena_bytes", "scratch_bytes", "out_bytes", "nsegments", "nroots")]
+                                   "arena_bytes", "scratch_bytes", "out_bytes", "nsegments", "nroots",
+                                   "unit_leaves", "max_unit_leaf_bytes")]
 
 
 class KernelArgs(ctypes.Structure):
@@ -138,6 +139,7 @@ _SIGS = {
     "dc_tree_objects": [vp, ctypes.POINTER(Object), u64, ctypes.POINTER(u64)],
     "dc_batch_run": [vp, ctypes.POINTER(KernelArgs), ctypes.POINTER(Tune), u32, vp],
     "dc_autotune": [vp, ctypes.POINTER(KernelArgs), u32, ctypes.POINTER(Tune)],
+    "dc_autotune_results": [vp, ctypes.POINTER(Tune), ctypes.POINTER(ctypes.c_double), u32, ctypes.POINTER(u32)],
     "dc_graph_create": [vp, ctypes.POINTER(KernelArgs), ctypes.POINTER(Tune), u32, ctypes.c_int, ctypes.c_int,
                         ctypes.POINTER(vp)],
     "dc_graph_launch": [vp, vp],
@@ -423,6 +425,16 @@ class Tree:
         _check(load().dc_autotune(self.h, ctypes.byref(ka), reps, ctypes.byref(tu)), "dc_autotune")
         return {"block": tu.block, "wg_per_cu": tu.wg_per_cu, "tile_chunks": tu.tile_chunks,
                 "launches": tu.launches}
+
+    def autotune_results(self) -> list:
+        """The candidates the last autotune timed: (shape, median microseconds)."""
+        n = u32()
+        _check(load().dc_autotune_results(self.h, None, None, 0, ctypes.byref(n)), "dc_autotune_results")
+        tunes = (Tune * max(n.value, 1))()
+        us = (ctypes.c_double * max(n.value, 1))()
+        _check(load().dc_autotune_results(self.h, tunes, us, n.value, ctypes.byref(n)), "dc_autotune_results")
+        return [({"block": t.block, "wg_per_cu": t.wg_per_cu, "tile_chunks": t.tile_chunks,
+                  "launches": t.launches}, us[i]) for i, t in enumerate(tunes[: n.value])]
 
     def graph(self, a=1.0001, b=0.5, tune=None, upload=False, download=False, out=None) -> "Graph":
         return Graph(self, a, b, tune, upload, download, out)

@@ -48,3 +48,24 @@ def test_cpu_baseline_fields():
     assert b["kind"] == "oracle" and b["cores"] == 1 and b["unit"] == "GB/s"
     assert b["value"] > 0 and b["seconds"] > 0
     assert "1 fma passes x 2 modes" in b["sample"]
+
+
+def test_cpu_baseline_md_fields():
+    """The batched workload's baseline: one thread on a sample, then every
+    simulation over the CPUs available, each credited with the GPU step's
+    algorithmic bytes of the same simulations."""
+    import bench
+    import fixtures as fx
+    t = fx.md(nsims=40)
+    b = bench.cpu_baseline_md(t, nsample=10, max_threads=4)
+    assert b["kind"] == "oracle" and b["unit"] == "GB/s" and b["value"] > 0
+    assert 1 <= b["cores"] <= 4 and b["cores"] <= b["cpus_available"]
+    assert b["cpu_model"] and "all 40 simulations" in b["sample"]
+    st = b["single_thread"]
+    assert st["cores"] == 1 and st["value"] > 0 and "first 10 simulations" in st["sample"]
+    # the credited bytes are those the GPU step moves for the same simulations
+    from paper_1906_01128_amd import dc
+    p = dc.Plan(dc.Schema(t.types), t.root_type, t.roots[:10])
+    assert st["bytes"] == bench.md_step_bytes(p.info())
+    i = p.info()
+    assert st["bytes"] == 2 * i.leaf_bytes + 2 * (16 * i.nslots_nonnull + 8 * i.nslots + 16 * i.nobjects)

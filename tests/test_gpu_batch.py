@@ -40,17 +40,79 @@ def test_batch_md_attach(ctx):
     assert c.tree.resolve_chain([(0, 3), (2, 0)], root_index=7) == c.oracle.resolve_chain(7, [(0, 3), (2, 0)])
 
 
-@pytest.mark.parametrize("tune", [None, dict(block=256, wg_per_cu=2, tile_chunks=1024),
-                                  dict(block=512, wg_per_cu=8, tile_chunks=4096),
-                                  dict(block=1024, wg_per_cu=1, tile_chunks=65536),
-                                  dict(block=256, wg_per_cu=4, tile_chunks=1 << 20),
-                                  dict(tile_chunks=1024, launches=1), dict(tile_chunks=4096, launches=1)])
+SHAPES = [None,
+          # one persistent launch, one relocation unit per item
+          dict(block=256, wg_per_cu=8, launches=0), dict(block=512, wg_per_cu=4, launches=0),
+          dict(block=1024, wg_per_cu=2, launches=0), dict(block=256, wg_per_cu=1, launches=0),
+          # one persistent launch in three phases
+          dict(block=256, wg_per_cu=2, tile_chunks=1024, launches=2),
+          dict(block=512, wg_per_cu=4, tile_chunks=4096, launches=2),
+          dict(block=1024, wg_per_cu=1, tile_chunks=65536, launches=2),
+          dict(block=256, wg_per_cu=4, tile_chunks=1 << 20, launches=2),
+          # three launches
+          dict(tile_chunks=1024, launches=1), dict(tile_chunks=4096, launches=1)]
+
+
+@pytest.mark.parametrize("tune", SHAPES)
 def test_batch_attach_detach_any_tile_shape(ctx, tune):
     t = fx.md(seed=5, nsims=60, cells_lo=1, cells_hi=40, mean_atoms=5)
     c = Copy(ctx, t, relocate=False)
+    assert c.plan.info().unit_leaves == 1
     want = _staged_after_kernel(c, 1)
     c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=tune)
     assert_same_bytes(c.device_arena(), want, f"batched attach+compute+detach {tune}")
+    c.tree.check()
+
+
+@pytest.mark.parametrize("launches", [0, 1, 2])
+def test_batch_each_flag_combination(ctx, launches):
+    """ATTACH alone, then neither (compute on the attached tree), then DETACH
+    alone, each compared with the oracle's arena at that point: attached and
+    advanced one pass, two passes, then staged again after three."""
+    t = fx.md(seed=15, nsims=80, cells_lo=1, cells_hi=60, mean_atoms=7)
+    c = Copy(ctx, t, relocate=False)
+    tune = dict(block=512, wg_per_cu=2, tile_chunks=2048, launches=launches)
+    ref = c.oracle
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=False, tune=tune)
+    ref.run_kernel(1.0001, 0.5, iters=1, select="all")
+    assert_same_bytes(c.device_arena(), ref.arena(), f"attach only, launches {launches}")
+    c.tree.batch_run(a=1.0001, b=0.5, attach=False, detach=False, tune=tune)
+    ref.run_kernel(1.0001, 0.5, iters=1, select="all")
+    assert_same_bytes(c.device_arena(), ref.arena(), f"compute only, launches {launches}")
+    c.tree.batch_run(a=1.0001, b=0.5, attach=False, detach=True, tune=tune)
+    assert_same_bytes(c.device_arena(), _staged_after_kernel(c, 3), f"detach only, launches {launches}")
+    c.tree.check()
+
+
+@pytest.mark.parametrize("launches", [0, 2])
+def test_batch_units_not_contiguous(ctx, launches):
+    """A 16-way Dense tree: its relocation units do not own contiguous leaf
+    runs, so the persistent launch runs in three phases either way."""
+    t = fx.dense(seed=44, q=16, n=10, D=3)
+    c = Copy(ctx, t, relocate=False)
+    assert c.plan.info().unit_leaves == 0
+    want = _staged_after_kernel(c, 1)
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=dict(block=256, wg_per_cu=4, launches=launches))
+    assert_same_bytes(c.device_arena(), want, f"dense q=16 launches {launches}")
+    c.tree.check()
+
+
+@pytest.mark.parametrize("tune", [dict(block=256, wg_per_cu=1, launches=0),
+                                  dict(block=256, wg_per_cu=1, tile_chunks=4096, launches=2)])
+def test_batch_many_items_per_workgroup(ctx, tune):
+    """600 simulations (~0.7 GB) on one 256-thread workgroup per compute unit:
+    every workgroup takes several relocation units (per-unit form), or, in
+    three phases, several relocation units and then some twenty batches of
+    two compute tiles each, with its phase waits contended by every other
+    workgroup. The whole arena is compared with the oracle."""
+    fx.set_threads(0)
+    t = fx.md(seed=21, nsims=600)
+    c = Copy(ctx, t, relocate=False)
+    info = c.plan.info()
+    print(f"[md 600] objects {info.nobjects} units {info.nsegments} arena {info.arena_bytes} {tune}", flush=True)
+    want = _staged_after_kernel(c, 1)
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=tune)
+    assert_same_bytes(c.device_arena(), want, f"md 600 sims {tune}")
     c.tree.check()
 
 
@@ -119,7 +181,11 @@ def test_autotune_then_parity(ctx, tmp_path, monkeypatch):
     t = fx.md(seed=8, nsims=200, cells_lo=4, cells_hi=64, mean_atoms=16)
     c = Copy(ctx, t, relocate=False)
     choice = c.tree.autotune(reps=1)
-    assert choice["block"] in (256, 512, 1024) and choice["launches"] in (0, 1)
+    assert choice["block"] in (256, 512, 1024) and choice["launches"] in (0, 1, 2)
+    table = c.tree.autotune_results()
+    assert len(table) >= 8 and choice in [tu for tu, _ in table]
+    assert all(tu["block"] * tu["wg_per_cu"] <= 2048 for tu, _ in table if tu["launches"] != 1)
+    assert any(tu["block"] == 1024 for tu, _ in table)
     assert (tmp_path / "tune.json").exists()
     # the autotuner changed leaf values; copy again and run with the cached choice
     t2 = fx.md(seed=8, nsims=200, cells_lo=4, cells_hi=64, mean_atoms=16)
@@ -129,24 +195,49 @@ def test_autotune_then_parity(ctx, tmp_path, monkeypatch):
     assert_same_bytes(c2.device_arena(), c2.oracle.arena(), "after autotune")
 
 
-@pytest.mark.slow
-def test_batch_md_full_size(ctx):
-    """10,000 simulations, ~7.8 M arrays, ~12 GB: one persistent launch,
-    compared with the oracle over the whole arena."""
+@pytest.fixture(scope="module")
+def md_full(ctx):
+    """The full MD workload, planned once, with device buffers and the
+    oracle's copy at the same arena address advanced by one pass: every
+    full-size case stages the tree again into the same buffers."""
+    from paper_1906_01128_amd import dc
     fx.set_threads(0)
     t = fx.md()
-    c = Copy(ctx, t, relocate=False)
-    info = c.plan.info()
-    print(f"[md full] objects {info.nobjects} slots {info.nslots_nonnull} arena {info.arena_bytes}", flush=True)
-    c.tree.batch_run(a=1.0001, b=0.5, attach=True)
-    c.oracle.run_kernel(1.0001, 0.5, iters=1, select="all")
+    schema = dc.Schema(t.types)
+    plan = dc.Plan(schema, t.root_type, t.roots)
+    arena = torch.empty(plan.arena_bytes, dtype=torch.uint8, device="cuda")
+    scratch = torch.empty(plan.scratch_bytes, dtype=torch.uint8, device="cuda")
+    ref = orc.OracleCopy(t.types, t.root_type, t.roots, 64, arena.data_ptr())
+    ref.run_kernel(1.0001, 0.5, iters=1, select="all")
+    yield t, schema, plan, arena, scratch, ref
+    ref.free()
+    del arena, scratch
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("tune", [dict(block=1024, wg_per_cu=2, launches=0),
+                                  dict(block=1024, wg_per_cu=2, tile_chunks=16384, launches=2),
+                                  dict(tile_chunks=1024, launches=1)])
+def test_batch_md_full_size(ctx, md_full, tune):
+    """10,000 simulations, ~7.8 M arrays, ~12 GB, in each batched form with
+    an explicit shape (the per-unit persistent launch, the three-phase
+    persistent launch in the shape the bench measures, three launches),
+    attached and advanced one pass, compared with the oracle over the whole
+    arena."""
+    from paper_1906_01128_amd import dc
+    t, schema, plan, arena, scratch, ref = md_full
+    info = plan.info()
+    print(f"[md full] objects {info.nobjects} slots {info.nslots_nonnull} arena {info.arena_bytes} {tune}", flush=True)
+    tree = dc.Tree(ctx, plan, arena, scratch, relocate=False)
+    tree.batch_run(a=1.0001, b=0.5, attach=True, tune=tune)
     torch.cuda.synchronize()
-    got = c.arena[: c.plan.arena_bytes].cpu().numpy()
-    want = c.oracle.arena()
+    got = arena[: plan.arena_bytes].cpu().numpy()
+    want = ref.arena()
     step = 1 << 30
     for lo in range(0, len(want), step):
-        assert np.array_equal(got[lo:lo + step], want[lo:lo + step]), f"md full arena differs in GiB {lo >> 30}"
-    c.tree.check()
+        assert np.array_equal(got[lo:lo + step], want[lo:lo + step]), f"md full arena differs in GiB {lo >> 30} {tune}"
+    tree.check()
+    tree.release()
 
 
 def test_forced_wait_bound_is_reported_and_the_launch_ends(ctx):

@@ -97,6 +97,6 @@ def _functions_importing_oracle(path):
 
 def test_only_the_baseline_smoke_and_build_touch_the_oracle():
     fns, top = _functions_importing_oracle(os.path.join(ROOT, "bench.py"))
-    assert fns == ["cpu_baseline_linear"] and not top
+    assert fns == ["cpu_baseline_linear", "cpu_baseline_md"] and not top
     fns, top = _functions_importing_oracle(os.path.join(ROOT, "__graft_entry__.py"))
     assert set(fns) <= {"build", "smoke"} and not top

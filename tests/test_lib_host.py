@@ -98,6 +98,25 @@ def test_plan_segments_cover_many_targets():
     assert p.info().nsegments >= 2
 
 
+def test_unit_leaf_runs():
+    """The per-unit persistent batched form needs every relocation unit's
+    slots to be the first to reach one contiguous run of leaves. The MD,
+    wide, plain, broom and Linear shapes have it (their structs list leaf
+    members before deeper struct members, so a depth-first layout places a
+    unit's leaves together); the 16-way Dense tree, whose nodes reach their
+    own array and then their children's subtrees, spreads over several
+    units that do not."""
+    for t in (fx.md(nsims=50), fx.wide(f1=8, f2=16), fx.plain(nchild=20000, leaf_len=1),
+              fx.broom(seed=3, bytes_hi=1 << 16), fx.linear(k=10, n=100, scheme=0)):
+        i = plan_of(t).info()
+        assert i.unit_leaves == 1
+        assert 0 < i.max_unit_leaf_bytes <= i.leaf_bytes + 16 * i.nleaves
+    i = plan_of(fx.md(nsims=50)).info()
+    assert i.nsegments > 100 and i.max_unit_leaf_bytes < i.leaf_bytes // 50
+    i = plan_of(fx.dense(q=16, n=10, D=3)).info()
+    assert i.nsegments > 1 and i.unit_leaves == 0
+
+
 def test_plan_errors_match_oracle():
     from paper_1906_01128_amd import dc
     types = fx.RANDOM_TYPES
