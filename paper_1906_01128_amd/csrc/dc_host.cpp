@@ -256,6 +256,18 @@ dc_status download(dc_ctx ctx, const uint8_t* src, uint64_t lo, uint64_t hi, hip
 
 static bool valid_kind(uint32_t k) { return k <= DC_KIND_U8; }
 
+// Threads for packing and scattering: the CPUs this process may run on,
+// capped by OMP_NUM_THREADS when that is set and by 32.
+int host_threads() {
+  int n = 0;
+  cpu_set_t set;
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) n = CPU_COUNT(&set);
+  if (n <= 0) n = (int)std::thread::hardware_concurrency();
+  const char* omp = getenv("OMP_NUM_THREADS");
+  if (omp && atoi(omp) > 0) n = std::min(n, atoi(omp));
+  return std::max(1, std::min(n, 32));
+}
+
 }  // namespace dc
 
 using namespace dc;
@@ -265,18 +277,6 @@ extern "C" {
 const char* dc_last_error(void) { return dc::g_err.c_str(); }
 
 const char* dc_version(void) { return "libdc 0.1 (gfx950)"; }
-
-// Threads for packing and scattering: the CPUs this process may run on,
-// capped by OMP_NUM_THREADS when that is set and by 32.
-static int host_threads() {
-  int n = 0;
-  cpu_set_t set;
-  if (sched_getaffinity(0, sizeof(set), &set) == 0) n = CPU_COUNT(&set);
-  if (n <= 0) n = (int)std::thread::hardware_concurrency();
-  const char* omp = getenv("OMP_NUM_THREADS");
-  if (omp && atoi(omp) > 0) n = std::min(n, atoi(omp));
-  return std::max(1, std::min(n, 32));
-}
 
 dc_status dc_ctx_create(int device, dc_ctx* out) {
   if (!out) return fail(DC_E_INVAL, "dc_ctx_create: out is null");

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <condition_variable>
 #include <functional>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -35,6 +36,30 @@ void clear_error();
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// Allocator whose resize leaves new elements default-initialised (no zero
+// fill), for the planner's large tables that are written in parallel right
+// after they are sized.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new ((void*)p) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
+template <class T>
+using bigvec = std::vector<T, NoInitAlloc<T>>;
+
 // ---- a small fork-join pool -------------------------------------------------------------
 class Pool {
  public:
@@ -57,6 +82,10 @@ class Pool {
   uint64_t gen_ = 0;
   bool stop_ = false;
 };
+
+// host threads a pool should use: the CPUs this process may run on, capped
+// by OMP_NUM_THREADS and at 32
+int host_threads();
 
 // ---- staging: pinned ring of chunks between pageable host memory and the device ---------------
 // A "piece" is a run of bytes at a fixed destination offset; gaps between
@@ -176,18 +205,17 @@ struct dc_plan_s {
   uint64_t align = 64;
   std::vector<uint64_t> roots;  // host addresses as given
   std::vector<uint32_t> root_obj;
-  std::vector<dc::Obj> objs;
-  dc::FlatMap map;
+  dc::bigvec<dc::Obj> objs;
   // slotted struct arrays (arena order) and their slot prefix
   std::vector<dc::DevSObj> sobj;
   std::vector<uint64_t> sobj_pre;
-  std::vector<uint32_t> slot_target;  // per slot: target object or kNone
+  dc::bigvec<uint32_t> slot_target;  // per slot: target object or kNone
   // relocation units
   std::vector<dc::DevSeg> segs;
   std::vector<dc::DevTarget> tgts;
   // leaves (FP32/FP64 arrays with >= 1 element), arena order
-  std::vector<uint32_t> leaves;
-  std::vector<uint64_t> leaf_pre, leaf_info, leaf_slot, leaf_out;
+  dc::bigvec<uint32_t> leaves;
+  dc::bigvec<uint64_t> leaf_pre, leaf_info, leaf_slot, leaf_out;
   uint64_t out_bytes = 0, total_chunks = 0, total_hops = 0;
   // every relocation unit's slots discover a contiguous run of leaves (in
   // leaf order), recorded in its DevSeg: the persistent launch can then run

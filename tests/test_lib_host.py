@@ -154,6 +154,84 @@ def test_plan_errors_match_oracle():
     assert ed.value.name == "INVAL"
 
 
+# ---- plans over many roots: walked in chunks of consecutive roots on host threads ----------
+
+
+def test_plan_many_independent_roots_matches_oracle():
+    """300 MD simulations: the chunked walk is kept (no array is reached from
+    two chunks) and must equal the walk in root order object by object."""
+    p, _ = _compare(fx.md(seed=77, nsims=300))
+    assert p.info().nroots == 300 and p.info().unit_leaves == 1
+
+
+@pytest.mark.slow
+def test_plan_full_md_matches_oracle():
+    """The full batched MD workload (10,000 simulations, ~7.75 M arrays):
+    the chunked plan equals the oracle's walk object by object."""
+    fx.set_threads(0)
+    t = fx.md()
+    p = plan_of(t)
+    c = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 0)
+    same_objects(p.objects(), c.objects())
+    assert p.info().arena_bytes == c.arena_bytes and p.info().nslots_nonnull == c.nslots
+    assert p.info().unit_leaves == 1
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_plan_many_roots_with_shared_arrays_matches_oracle(seed):
+    """Random graphs over 200 roots whose structs point into other roots'
+    arrays (aliases, cycles, zero-length arrays): the chunked walk sees an
+    array reached from two chunks and the walk in root order decides."""
+    _compare(fx.random_tree(900 + seed, max_objects=3000, nroots=200), align=[16, 64, 256, 4096][seed])
+
+
+def _md_roots(n):
+    t = fx.md(seed=78, nsims=n, cells_lo=2, cells_hi=6, mean_atoms=3)
+    cells = [int.from_bytes(ctypes.string_at(r + 8, 8), "little") for r in t.roots]
+    return t, cells
+
+
+def test_plan_many_roots_aliases_and_errors_match_oracle():
+    """Across chunks: an array shared by two roots is copied once (as the walk
+    in root order does), a pointer into the middle of another root's array
+    is DC_E_RANGE, the same array reached with another length is
+    DC_E_CONFLICT, and a negative count in a late root is DC_E_INVAL."""
+    from paper_1906_01128_amd import dc
+
+    def put(a, off, v, signed=False):
+        ctypes.memmove(a + off, int(v).to_bytes(8, "little", signed=signed), 8)
+
+    def both(t):
+        try:
+            c = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 0)
+        except orc.OracleError as e:
+            with pytest.raises(dc.DcError) as ed:
+                plan_of(t)
+            assert ed.value.name == e.name
+            return e.name
+        p = plan_of(t)
+        same_objects(p.objects(), c.objects())
+        assert p.info().arena_bytes == c.arena_bytes
+        return "OK"
+
+    t, cells = _md_roots(200)
+    put(t.roots[180], 8, cells[20])             # root 180 shares root 20's cells (same count?)
+    put(t.roots[180], 0, int.from_bytes(ctypes.string_at(t.roots[20], 8), "little"), True)
+    assert both(t) == "OK"
+    t, cells = _md_roots(200)
+    put(t.roots[190], 8, cells[10] + 32)        # one cell into root 10's array
+    put(t.roots[190], 0, 1, True)
+    assert both(t) == "RANGE"
+    t, cells = _md_roots(200)
+    n10 = int.from_bytes(ctypes.string_at(t.roots[10], 8), "little")
+    put(t.roots[170], 8, cells[10])             # root 10's cells with one cell more
+    put(t.roots[170], 0, n10 + 1, True)
+    assert both(t) == "CONFLICT"
+    t, cells = _md_roots(200)
+    put(t.roots[150], 0, -1, True)
+    assert both(t) == "INVAL"
+
+
 # ---- dc_chain_query: the host walk of the pointerchain transfer (no device) ----------------
 
 
