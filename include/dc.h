@@ -422,7 +422,9 @@ dc_status dc_batch_run(dc_tree tree, const dc_kernel_args* args, const dc_tune* 
  * tree (which leaves its leaf values changed: deep copy again before a run
  * whose values matter) and returns the fastest; the choice is cached on disk
  * keyed by device and workload shape (DC_TUNE_CACHE, default
- * ~/.cache/dc_tune.json). Errors: DC_E_INVAL for a NULL argument or args
+ * ~/.cache/dc_tune.json). Synchronous: it first waits for all work queued on
+ * the device (the tree's deep copy may still be in flight on the caller's
+ * stream), then times the candidates on a stream of its own. Errors: DC_E_INVAL for a NULL argument or args
  * other than RESOLVED, ALL_LEAVES, one pass; DC_E_STATE if the tree is
  * attached or a device check fails; DC_E_RANGE for a d_out too small or
  * misaligned; DC_E_HIP. */
@@ -436,7 +438,9 @@ dc_status dc_autotune_results(dc_tree tree, dc_tune* tunes, double* us, uint32_t
 /* Captures dc_batch_run(tree, args, tune, flags) into a HIP graph; optionally
  * preceded by the host-to-device transfer of the staged image (upload != 0,
  * which keeps a pinned copy of the whole image) and followed by the transfer
- * back of the arena into pinned memory (download != 0). dc_graph_launch
+ * back of the arena into pinned memory (download != 0). Creation first waits
+ * for all work queued on the device (the tree's deep copy included) and
+ * returns when the capture is complete. dc_graph_launch
  * replays it; if a call with another tile size has rebuilt the tree's tile
  * list since the capture, the launch first rebuilds the captured one.
  * Errors (create): DC_E_INVAL for flags other than ATTACH|DETACH or bad args

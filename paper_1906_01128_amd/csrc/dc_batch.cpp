@@ -204,11 +204,18 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
   DC_TRY(batch_args(t, a, &la));
   if (reps == 0) reps = 3;
   DC_HIP(hipSetDevice(t->ctx->device));
+  // the candidates run on a stream of their own, which orders nothing with
+  // the caller's streams: the tree's deep copy (and whatever else the caller
+  // queued on it) must have completed first
+  DC_HIP(hipDeviceSynchronize());
   hipStream_t s;
   DC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-  hipEvent_t e0, e1;
-  DC_HIP(hipEventCreate(&e0));
-  DC_HIP(hipEventCreate(&e1));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipStreamDestroy(s);
+    return fail(DC_E_HIP, "autotune events");
+  }
   const uint32_t flags = DC_BATCH_ATTACH | DC_BATCH_DETACH;
   // Candidates: persistent shapes whose workgroups are all resident at once
   // (at most 2048 threads per compute unit), the per-unit form when the plan
@@ -287,35 +294,47 @@ dc_status dc_graph_create(dc_tree t, const dc_kernel_args* a, const dc_tune* tun
   DC_TRY(resolve_tune(t, tune, &tu));
   DC_HIP(hipSetDevice(t->ctx->device));
   dc_plan p = t->plan;
+  // the capture stream orders nothing with the caller's streams: the tree's
+  // deep copy must be complete before the tile list upload and the image
+  // read-back below
+  DC_HIP(hipDeviceSynchronize());
+  hipStream_t cs;
+  DC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   dc_graph g = new dc_graph_s();
   g->tree = t;
   auto cleanup = [&](dc_status st) {
+    if (cs) (void)hipStreamDestroy(cs);
     dc_graph_destroy(g);
     return st;
   };
-  hipStream_t cs;
-  DC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  auto hip_fail = [&](hipError_t e, const char* what) {
+    return cleanup(fail(DC_E_HIP, "%s: %s", what, hipGetErrorString(e)));
+  };
   // the tile index is built outside the graph; the graph only replays the launch
   if (uses_tiles(t, tu, flags)) {
     dc_status st = tree_ensure_tiles(t, tu.tile_chunks, cs);
     if (st != DC_OK) return cleanup(st);
     g->tile_T = tu.tile_chunks;
   }
+  hipError_t e;
   if (upload) {
     if (hipHostMalloc((void**)&g->up, std::max<uint64_t>(p->arena_bytes, 1), hipHostMallocDefault) != hipSuccess)
       return cleanup(fail(DC_E_NOMEM, "pinned image of %llu bytes", (unsigned long long)p->arena_bytes));
     // the staged image is what the arena holds now: read it back once
-    if (p->arena_bytes) DC_HIP(hipMemcpyAsync(g->up, t->arena, p->arena_bytes, hipMemcpyDeviceToHost, cs));
+    if (p->arena_bytes &&
+        (e = hipMemcpyAsync(g->up, t->arena, p->arena_bytes, hipMemcpyDeviceToHost, cs)) != hipSuccess)
+      return hip_fail(e, "image read-back");
   }
   if (download && hipHostMalloc((void**)&g->down, std::max<uint64_t>(p->arena_bytes, 1), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(DC_E_NOMEM, "pinned image of %llu bytes", (unsigned long long)p->arena_bytes));
-  DC_HIP(hipStreamSynchronize(cs));
-  DC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  if ((e = hipStreamSynchronize(cs)) != hipSuccess) return hip_fail(e, "graph set-up");
+  if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return hip_fail(e, "begin capture");
   if (upload && p->arena_bytes) (void)hipMemcpyAsync(t->arena, g->up, p->arena_bytes, hipMemcpyHostToDevice, cs);
   dc_status st = enqueue_batch(t, la, tu, flags, cs, true);
   if (download && p->arena_bytes) (void)hipMemcpyAsync(g->down, t->arena, p->arena_bytes, hipMemcpyDeviceToHost, cs);
-  hipError_t e = hipStreamEndCapture(cs, &g->graph);
+  e = hipStreamEndCapture(cs, &g->graph);
   (void)hipStreamDestroy(cs);
+  cs = nullptr;
   if (st != DC_OK) return cleanup(st);
   if (e != hipSuccess) return cleanup(fail(DC_E_HIP, "graph capture: %s", hipGetErrorString(e)));
   e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);

@@ -264,3 +264,42 @@ def test_forced_wait_bound_is_reported_and_the_launch_ends(ctx):
     c2.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=dict(tune, spin_limit=0))
     assert_same_bytes(c2.device_arena(), want, "persistent launch after a forced wait bound")
     c2.tree.check()
+
+
+def test_autotune_and_graph_right_after_staging(ctx, tmp_path, monkeypatch):
+    """The autotuner and the graph capture run on streams of their own; called
+    right after staging, with the staging copies still in flight on the
+    caller's stream, they must wait for them (a ~0.6 GB tree, as the bench's
+    500-simulation comparison stages just before autotuning)."""
+    from paper_1906_01128_amd import dc
+    monkeypatch.setenv("DC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    fx.set_threads(0)
+    t = fx.md(seed=31, nsims=500)
+    schema = dc.Schema(t.types)
+    plan = dc.Plan(schema, t.root_type, t.roots)
+    arena = torch.empty(plan.arena_bytes, dtype=torch.uint8, device="cuda")
+    scratch = torch.empty(plan.scratch_bytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    print(f"[gpu] stage then autotune at once: {plan.arena_bytes} B", flush=True)
+    tree = dc.Tree(ctx, plan, arena, scratch, relocate=False)
+    tree.autotune(reps=1)
+    tree.check()
+    tree.release()
+    # stage again and capture with the image upload at once: the captured
+    # image must be the staged one
+    tree = dc.Tree(ctx, plan, arena, scratch, relocate=False)
+    g = tree.graph(a=1.0001, b=0.5, tune=dict(tile_chunks=1024, launches=1), upload=True)
+    g.launch()
+    torch.cuda.synchronize()
+    ref = orc.OracleCopy(t.types, t.root_type, t.roots, 64, arena.data_ptr())
+    ref.run_kernel(1.0001, 0.5, iters=1, select="all")
+    img = ref.arena().copy()
+    for o in ref.objects():    # staged again after the replay's detach: host pointers in the slots
+        if o["kind"] == 0 and o["bytes"]:
+            lo, hi = int(o["off"]), int(o["off"]) + int(o["bytes"])
+            img[lo:hi] = np.frombuffer(ctypes.string_at(int(o["host"]), int(o["bytes"])), np.uint8)
+    assert_same_bytes(arena[: plan.arena_bytes].cpu().numpy(), img, "graph captured right after staging")
+    tree.check()
+    g.close()
+    tree.release()
+    ref.free()
