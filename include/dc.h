@@ -206,6 +206,28 @@ dc_status dc_plan_objects(dc_plan plan, dc_object* out, uint64_t cap, uint64_t* 
 dc_status dc_deep_copy_to_device(dc_ctx ctx, dc_plan plan, void* d_arena, uint64_t arena_bytes, void* d_scratch,
                                  uint64_t scratch_bytes, void* stream, dc_tree* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the deep copy
+ * of dc_deep_copy_to_device, with the relocation tables and the device header
+ * in a fixed array of DC_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * device from its load until the process ends, instead of a caller scratch
+ * buffer. Makes no device or pinned allocation (the staging ring and the
+ * array's address are set up by dc_ctx_create). The tree it returns works
+ * with every other call. One such tree at a time per device: the array keeps
+ * the last copy's tables, so while a tree made here is alive, another call on
+ * the same device returns DC_E_STATE; dc_tree_release of such a tree first
+ * waits until the device is idle (nothing queued still reads its tables),
+ * then frees the array for the next call. Calls for one device from several
+ * threads are serialised by that rule; a caller that bypasses it by using a
+ * released tree races with the next copy. d_arena as for
+ * dc_deep_copy_to_device. Errors: DC_E_RANGE if the plan's tables (the
+ * scratch_bytes dc_plan_create reported) exceed DC_NOALLOC_SCRATCH_BYTES or
+ * d_arena is too small or misaligned; DC_E_STATE as above; DC_E_INVAL for
+ * NULL arguments; DC_E_HIP. */
+#define DC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+dc_status dc_deep_copy_to_device_noalloc(dc_ctx ctx, dc_plan plan, void* d_arena, uint64_t arena_bytes, void* stream,
+                                         dc_tree* out);
+
 /* Like dc_deep_copy_to_device but without the relocation: the arena holds
  * the host bytes verbatim (host addresses in every pointer member) until
  * dc_attach or dc_batch_run relocates it. Errors: as dc_deep_copy_to_device. */

@@ -305,6 +305,12 @@ dc_status dc_ctx_create(int device, dc_ctx* out) {
     dc_ctx_destroy(c);
     return fail(DC_E_NOMEM, "dc_ctx_create: device header");
   }
+  // the fixed scratch of the no-allocation deep copy: its address on this device
+  const dc_status st = noalloc_setup(device);
+  if (st != DC_OK) {
+    dc_ctx_destroy(c);
+    return st;
+  }
   c->pool = new Pool(host_threads());
   *out = c;
   clear_error();

@@ -244,9 +244,19 @@ struct dc_tree_s {
   hipEvent_t tiles_ev = nullptr;    // recorded after the tile index was built
   dc::KdTables* kd = nullptr;       // element list of the kick-drift kernel (device)
   std::vector<std::pair<dc_tune, double>> tune_table;  // the last autotune: shape, median us
+  int noalloc_dev = -1;             // device whose fixed scratch array this tree holds (-1: caller scratch)
 };
 
 namespace dc {
+// The deep copy into caller (or fixed) device buffers; attach: relocate too.
+dc_status deep_copy(dc_ctx ctx, dc_plan p, void* d_arena, uint64_t arena_bytes, void* d_scratch,
+                    uint64_t scratch_bytes, void* stream, bool attach, dc_tree* out);
+// Size of the fixed per-device scratch of dc_deep_copy_to_device_noalloc.
+constexpr uint64_t kNoAllocScratchBytes = DC_NOALLOC_SCRATCH_BYTES;
+// Looks up the fixed scratch array on `device` (current); once per device.
+dc_status noalloc_setup(int device);
+// A tree holding the device's fixed scratch was released.
+void noalloc_release(int device);
 dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, const void* const* roots,
                      uint64_t nroots, uint64_t align, const uint32_t* follow = nullptr, uint32_t nfollow = 0);
 // Uploads the tile list for tiles of T chunks if scratch holds another size,

@@ -100,8 +100,8 @@ static PieceSource arena_source(dc_plan p) {
   return src;
 }
 
-static dc_status deep_copy(dc_ctx ctx, dc_plan p, void* d_arena, uint64_t arena_bytes, void* d_scratch,
-                           uint64_t scratch_bytes, void* stream, bool attach, dc_tree* out) {
+dc_status deep_copy(dc_ctx ctx, dc_plan p, void* d_arena, uint64_t arena_bytes, void* d_scratch,
+                    uint64_t scratch_bytes, void* stream, bool attach, dc_tree* out) {
   if (!out) return fail(DC_E_INVAL, "out is null");
   *out = nullptr;
   if (!ctx || !p) return fail(DC_E_INVAL, "null context or plan");
@@ -473,6 +473,13 @@ dc_status dc_tree_release(dc_tree t) {
   t->released = true;
   if (t->tiles_ev) (void)hipEventDestroy(t->tiles_ev);
   kd_free(t);
+  if (t->noalloc_dev >= 0) {
+    // the device's fixed scratch is free for the next no-allocation copy once
+    // nothing queued still reads this tree's tables from it
+    (void)hipSetDevice(t->ctx->device);
+    (void)hipDeviceSynchronize();
+    noalloc_release(t->noalloc_dev);
+  }
   delete t;
   return DC_OK;
 }

@@ -23,6 +23,7 @@ KIND = {"struct": 0, "f32": 1, "f64": 2, "i32": 3, "i64": 4, "u8": 5}
 KIND_NAME = {v: k for k, v in KIND.items()}
 MODE = {"resolved": 0, "deref_each": 1}
 SELECT = {"chain": 0, "all": 1}
+NOALLOC_SCRATCH_BYTES = 64 << 20   # DC_NOALLOC_SCRATCH_BYTES of include/dc.h
 COPY_LEAVES, COPY_SCALARS = 1, 2
 BATCH_ATTACH, BATCH_DETACH, BATCH_FORCE_WAIT_BOUND = 1, 2, 4
 
@@ -120,6 +121,7 @@ _SIGS = {
     "dc_plan_objects": [vp, ctypes.POINTER(Object), u64, ctypes.POINTER(u64)],
     "dc_deep_copy_to_device": [vp, vp, vp, u64, vp, u64, vp, ctypes.POINTER(vp)],
     "dc_stage_to_device": [vp, vp, vp, u64, vp, u64, vp, ctypes.POINTER(vp)],
+    "dc_deep_copy_to_device_noalloc": [vp, vp, vp, u64, vp, ctypes.POINTER(vp)],
     "dc_attach": [vp, vp],
     "dc_detach": [vp, vp],
     "dc_resolve_chain": [vp, u64, ctypes.POINTER(Step), u32, vp, ctypes.POINTER(Chain)],
@@ -338,6 +340,19 @@ class Tree:
                   _stream_ptr(stream), ctypes.byref(h)), "dc_deep_copy_to_device" if relocate else "dc_stage_to_device")
         self.h = h
         self.ctx, self.plan, self.arena, self.scratch = ctx, plan, arena, scratch
+
+    @classmethod
+    def noalloc(cls, ctx: Context, plan: Plan, arena, stream=None) -> "Tree":
+        """dc_deep_copy_to_device_noalloc: the deep copy with the relocation
+        tables in the library's fixed per-device array (no scratch tensor)."""
+        h = vp()
+        _check(load().dc_deep_copy_to_device_noalloc(ctx.h, plan.h, _dev_ptr(arena), arena.numel(),
+                                                     _stream_ptr(stream), ctypes.byref(h)),
+               "dc_deep_copy_to_device_noalloc")
+        self = cls.__new__(cls)
+        self.h = h
+        self.ctx, self.plan, self.arena, self.scratch = ctx, plan, arena, None
+        return self
 
     def attach(self, stream=None):
         _check(load().dc_attach(self.h, _stream_ptr(stream)), "dc_attach")
