@@ -486,6 +486,10 @@ typedef struct {
   uint32_t max_inflight;   /* jobs on the device at once */
   uint32_t nstreams;       /* copy/compute streams */
   uint64_t align;          /* arena alignment (0: 64) */
+  uint32_t fail_copy_at;   /* tests of the error path only: the admission of the
+                              n-th new structure (1-based) fails after its deep
+                              copy, as a failing later step would; 0 = never */
+  uint32_t reserved;
 } dc_server_config;
 
 typedef struct {

@@ -98,6 +98,7 @@ struct Resident {
   uint8_t* scratch = nullptr;
   uint64_t bytes = 0;  // device bytes held
   int refs = 0;
+  bool ok = false;             // admitted whole: copy, tiles and ready event all done
   hipEvent_t ready = nullptr;  // recorded after the deep copy and relocation
   std::list<Resident*>::iterator lru;
 };
@@ -105,7 +106,8 @@ struct Resident {
 struct Job {
   uint64_t id = 0;
   dc_request req{};
-  dc_plan plan = nullptr;  // the job's own plan (dropped when a resident copy is reused)
+  dc_plan plan = nullptr;  // the job's own plan (none when its key was resident at submit;
+                           // dropped when a resident copy is reused)
   Resident* res = nullptr;
   uint8_t* d_out = nullptr;
   uint64_t out_bytes = 0;
@@ -139,6 +141,7 @@ struct dc_server_s {
   std::list<Resident*> lru;     // front = most recently used
   uint64_t next_id = 1;
   uint32_t active = 0;          // admitted, not finished
+  uint32_t new_structures = 0;  // admissions that copied a new structure
   bool stop = false;
   dc_server_stats stats{};
   std::thread issue_thr, done_thr;
@@ -201,6 +204,20 @@ dc_status dc_server_s::admit(Job* j, std::unique_lock<std::mutex>& lk) {
     auto it = residents.find(j->req.key);
     if (it != residents.end()) r = it->second;
   }
+  if (!r && !j->plan) {
+    // resident at submit, evicted since: plan it now (only this thread
+    // creates residents, so the key stays absent meanwhile)
+    lk.unlock();
+    const void* roots[1] = {j->req.root};
+    uint64_t ab = 0, sb = 0;
+    dc_status st = dc_plan_create(nullptr, schema, j->req.root_type, roots, 1, cfg.align, &j->plan, &ab, &sb);
+    dc_plan_info pi;
+    if (st == DC_OK && dc_plan_query(j->plan, &pi) == DC_OK && j->req.out_bytes < pi.out_bytes)
+      st = fail(DC_E_RANGE, "out_bytes %llu, the leaf image needs %llu", (unsigned long long)j->req.out_bytes,
+                (unsigned long long)pi.out_bytes);
+    lk.lock();
+    if (st != DC_OK) return st;
+  }
   const dc_plan p = r ? r->plan : j->plan;
   dc_plan_info info;
   dc_plan_query(p, &info);
@@ -254,9 +271,14 @@ dc_status dc_server_s::admit(Job* j, std::unique_lock<std::mutex>& lk) {
                                           info.scratch_bytes, s, &r->tree);
     // the tile list is part of the resident state that later jobs share
     if (st == DC_OK) st = tree_prepare_leaf_tiles(r->tree, s);
+    if (st == DC_OK && cfg.fail_copy_at && ++new_structures == cfg.fail_copy_at)
+      st = fail(DC_E_HIP, "admission failure injected after the deep copy of new structure %u", cfg.fail_copy_at);
     if (st == DC_OK && hipEventRecord(r->ready, s) != hipSuccess) st = fail(DC_E_HIP, "event record");
     lk.lock();
+    // a failed resident is never reused (the issue loop frees it): its copy
+    // may be partial and its ready event unrecorded
     if (st != DC_OK) return st;
+    r->ok = true;
     stats.h2d_bytes += info.arena_bytes + info.scratch_bytes;
   } else {
     j->res = r;
@@ -315,9 +337,14 @@ void dc_server_s::issue_loop() {
     pending.pop_front();
     if (st != DC_OK) {
       std::string err = dc_last_error();
+      // work the failed admission queued (transfers into the resident's
+      // memory, a kernel into d_out) must end before that memory is reused
+      lk.unlock();
+      (void)hipStreamSynchronize(streams[j->stream]);
+      lk.lock();
       if (j->res) {
         j->res->refs--;
-        if (!j->res->key || !j->res->tree) free_resident(j->res);
+        if (!j->res->key || !j->res->ok) free_resident(j->res);
         j->res = nullptr;
       }
       pool.release(j->d_out);
@@ -438,26 +465,40 @@ dc_status dc_server_submit(dc_server s, const dc_request* req, uint64_t* id) {
   auto j = std::make_unique<Job>();
   j->req = *req;
   j->t_submit = now_s();
-  // plan now, on the caller's thread: sizes decide admission
-  const void* roots[1] = {req->root};
-  uint64_t ab = 0, sb = 0;
-  DC_TRY(dc_plan_create(nullptr, s->schema, req->root_type, roots, 1, s->cfg.align, &j->plan, &ab, &sb));
-  dc_plan_info info;
-  dc_plan_query(j->plan, &info);
+  // a key that is resident now names an unchanged structure that was
+  // planned already: its plan gives the sizes. Otherwise plan now, on the
+  // caller's thread: sizes decide admission (a resident evicted before this
+  // job's admission is planned then)
+  dc_plan_info info{};
+  bool resident = false;
+  if (req->key) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->residents.find(req->key);
+    if (it != s->residents.end() && it->second->ok) {
+      dc_plan_query(it->second->plan, &info);
+      resident = true;
+    }
+  }
+  if (!resident) {
+    const void* roots[1] = {req->root};
+    uint64_t ab = 0, sb = 0;
+    DC_TRY(dc_plan_create(nullptr, s->schema, req->root_type, roots, 1, s->cfg.align, &j->plan, &ab, &sb));
+    dc_plan_query(j->plan, &info);
+  }
   if (req->out_bytes < info.out_bytes) {
-    dc_plan_destroy(j->plan);
+    if (j->plan) dc_plan_destroy(j->plan);
     return fail(DC_E_RANGE, "out_bytes %llu, the leaf image needs %llu", (unsigned long long)req->out_bytes,
                 (unsigned long long)info.out_bytes);
   }
-  const uint64_t need = align_up(std::max<uint64_t>(ab, 1), 256) + align_up(sb, 256) +
+  const uint64_t need = align_up(std::max<uint64_t>(info.arena_bytes, 1), 256) + align_up(info.scratch_bytes, 256) +
                         align_up(std::max<uint64_t>(info.out_bytes, 1), 256);
   if (need > s->pool.size()) {
-    dc_plan_destroy(j->plan);
+    if (j->plan) dc_plan_destroy(j->plan);
     return fail(DC_E_BUDGET, "job needs %llu device bytes, budget is %llu", (unsigned long long)need,
                 (unsigned long long)s->pool.size());
   }
   if (hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming) != hipSuccess) {
-    dc_plan_destroy(j->plan);
+    if (j->plan) dc_plan_destroy(j->plan);
     return fail(DC_E_HIP, "event create");
   }
   std::lock_guard<std::mutex> lk(s->mu);

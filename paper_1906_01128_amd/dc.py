@@ -86,7 +86,8 @@ class Tune(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("budget_bytes", u64), ("max_inflight", u32), ("nstreams", u32), ("align", u64)]
+    _fields_ = [("budget_bytes", u64), ("max_inflight", u32), ("nstreams", u32), ("align", u64),
+                ("fail_copy_at", u32), ("reserved", u32)]
 
 
 class Request(ctypes.Structure):
@@ -557,8 +558,9 @@ class Server:
     """Continuous-batching deep-copy+kernel server (see dc_server_* in dc.h)."""
 
     def __init__(self, ctx: Context, schema: Schema, budget_bytes: int, max_inflight: int = 8, nstreams: int = 4,
-                 align: int = 64):
-        cfg = ServerConfig(budget_bytes, max_inflight, nstreams, align)
+                 align: int = 64, fail_copy_at: int = 0):
+        """fail_copy_at: tests of the error path only (dc_server_config)."""
+        cfg = ServerConfig(budget_bytes, max_inflight, nstreams, align, fail_copy_at, 0)
         h = vp()
         _check(load().dc_server_create(ctx.h, schema.h, ctypes.byref(cfg), ctypes.byref(h)), "dc_server_create")
         self.h = h
