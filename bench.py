@@ -695,6 +695,19 @@ def _batched_secondary(args, torch, dc, ctx, t, plan, tree, info, table):
                2: "persistent_phased"}[tu["launches"]]
         if key not in best or us < best[key]["us"]:
             best[key] = dict(tu, us=round(us, 1), GBps=round(step_bytes / us / 1e3, 1))
+    # attach and detach alone (the relocation kernel), medians of 5
+    rel = {"attach": [], "detach": []}
+    for _ in range(6):
+        for what in ("attach", "detach"):
+            e = _events(torch, 2)
+            e[0].record(s)
+            getattr(tree, what)()
+            e[1].record(s)
+            torch.cuda.synchronize()
+            rel[what].append(e[0].elapsed_time(e[1]) / 1e3)
+    rel_bytes = info.nslots_nonnull * 16 + info.nslots * 8 + info.nobjects * 16   # algorithmic, as in the step
+    att_s, det_s = pct(rel["attach"][1:], 50), pct(rel["detach"][1:], 50)
+    tree.check()
     # the MD kick-drift kernel on the same cells: v += f dt/m, x += v dt
     tree.attach()
     dt = 1e-3
@@ -713,6 +726,11 @@ def _batched_secondary(args, torch, dc, ctx, t, plan, tree, info, table):
     kd_gbps = kd_bytes / pct(kd, 50) / 1e9
     plain = _batched_vs_plain(torch, dc, ctx, t, None, nsub=500)
     return {"forms": best,
+            "relocation": {"kernel": "k_relocate", "attach_us": round(1e6 * att_s, 1), "detach_us": round(1e6 * det_s, 1),
+                           "bytes_per_launch": rel_bytes, "achieved_GBps": round(rel_bytes / att_s / 1e9, 1),
+                           "frac": round(rel_bytes / att_s / 1e9 / HBM_PEAK_GBPS, 4),
+                           "bytes": "8 B read + 8 B written per non-null slot, 8 B read per null slot, 16 B per "
+                                    "object (its target entry); the 2-byte target index per slot is not counted"},
             "kick_drift": {"kernel": "k_kick_drift", "ms": round(1e3 * pct(kd, 50), 3),
                            "bytes_per_launch": kd_bytes, "achieved_GBps": round(kd_gbps, 1),
                            "frac": round(kd_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic("batched", "k_kick_drift")},

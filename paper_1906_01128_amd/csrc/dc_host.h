@@ -213,6 +213,7 @@ struct dc_plan_s {
   // relocation units
   std::vector<dc::DevSeg> segs;
   std::vector<dc::DevTarget> tgts;
+  dc::bigvec<uint16_t> slot_tix;  // per slot: index of its target in its unit's targets
   // leaves (FP32/FP64 arrays with >= 1 element), arena order
   dc::bigvec<uint32_t> leaves;
   dc::bigvec<uint64_t> leaf_pre, leaf_info, leaf_slot, leaf_out;

@@ -18,12 +18,12 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 // Relocation work units ("segments"): a contiguous range of the global slot
 // enumeration (struct objects in arena order, elements in index order,
 // pointer members in ascending offset order) and the distinct objects its
-// non-null slots point to. A workgroup stages those objects' (key -> object)
-// pairs in an LDS hash table and translates every slot of the range.
-constexpr uint32_t kSegMaxTargets = 512;   // distinct targets per unit
-constexpr uint32_t kSegHashSlots = 1024;   // LDS hash capacity (load <= 1/2)
+// non-null slots point to. Every slot carries the index of its target in its
+// unit's target list; a workgroup stages the unit's targets (address before
+// and after the translation) in LDS and translates every slot of the range.
 constexpr uint32_t kSegMaxSObjs = 256;     // struct objects spanned per unit
-constexpr uint64_t kSegMaxSlots = 1024;    // slots per unit
+constexpr uint64_t kSegMaxSlots = 2048;    // slots per unit (so at most 2048 targets)
+constexpr uint16_t kNoTarget = 0xFFFF;     // slot index of a null (or unfollowed) slot
 
 constexpr uint32_t kChunk = 16;             // bytes per vector access of the leaf kernels
 
@@ -122,7 +122,7 @@ enum DevErr : uint32_t {
 };
 
 struct ScratchLayout {
-  uint64_t header, types, sobj, sobj_pre, segs, tgts;
+  uint64_t header, types, sobj, sobj_pre, segs, tgts, slot_tix;
   uint64_t leaf_slot, leaf_pre, leaf_info, leaf_out;
   uint64_t tiles, paths, hops;
   uint64_t static_end;  // [0, static_end) is uploaded with every deep copy
@@ -202,6 +202,7 @@ struct Tables {  // device addresses of the scratch tables
   const uint64_t* sobj_pre;  // nsobj + 1 entries (slot prefix)
   const DevSeg* segs;
   const DevTarget* tgts;  // every unit's targets, unit after unit
+  const uint16_t* slot_tix;  // per slot: its target's index in its unit's list, or kNoTarget
   const uint64_t* leaf_slot;
   const uint64_t* leaf_pre;  // nleaves + 1 entries (16-byte chunk prefix)
   const uint64_t* leaf_info;

@@ -12,7 +12,7 @@ namespace dc {
 
 namespace {
 
-constexpr int kRelocBlock = 256;
+constexpr int kRelocBlock = 512;
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -26,6 +26,38 @@ typedef __attribute__((address_space(1))) uint64_t g_u64;
 
 __device__ __forceinline__ u32x4 gload16(uint64_t a) { return *(const g_u32x4*)a; }
 __device__ __forceinline__ void gstore16(uint64_t a, u32x4 v) { *(g_u32x4*)a = v; }
+
+// Leaf data streamed once per pass. NT: non-temporal loads and stores, which
+// (both together; either alone changed nothing) ran a flat 12 GiB in-place
+// fma stream at 6.5 TB/s against 5.96 with plain accesses, and the MD
+// kick-drift kernel's five streams 5% faster. They are not used where leaves
+// are small: on the MD leaves (about 1.5 KB, so many 128-byte lines are
+// shared by two leaves or written in part) the tiled leaf kernel ran 2-11%
+// slower with them at every tile shape, and the per-unit persistent launch
+// 16% slower. Streams that fit the Infinity Cache and are read again pass
+// after pass keep plain accesses too (128 MiB: 6.66 TB/s plain, 6.38 NT).
+template <bool NT>
+__device__ __forceinline__ u32x4 sload16(uint64_t a) {
+  if constexpr (NT) return __builtin_nontemporal_load((const g_u32x4*)a);
+  else return *(const g_u32x4*)a;
+}
+template <bool NT>
+__device__ __forceinline__ void sstore16(uint64_t a, u32x4 v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, (g_u32x4*)a);
+  else *(g_u32x4*)a = v;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ T sload(uint64_t a) {
+  typedef __attribute__((address_space(1))) T gT;
+  if constexpr (NT) return __builtin_nontemporal_load((const gT*)a);
+  else return *(const gT*)a;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void sstore(uint64_t a, T v) {
+  typedef __attribute__((address_space(1))) T gT;
+  if constexpr (NT) __builtin_nontemporal_store(v, (gT*)a);
+  else *(gT*)a = v;
+}
 
 // Workgroup barrier that orders LDS accesses only. __syncthreads() also
 // orders global memory, which on CDNA means waiting until every store of the
@@ -45,15 +77,16 @@ struct RelocType {
   uint32_t ptr_off[kMaxFields];
 };
 
-// LDS of one relocation unit: an open-addressing hash from a slot's current
-// value to its translated value, and the struct arrays the unit spans (their
-// placement, and their slot prefix relative to the unit's first slot), then
-// the types of the plan, so that a slot costs one global load (its value) and
-// one store. About 19.5 KB plus 80 bytes per type: eight workgroups of a
+// LDS of one relocation unit: every target's address before and after the
+// translation, indexed by the target index each slot carries, and the struct
+// arrays the unit spans (their placement, and their slot prefix relative to
+// the unit's first slot), then the types of the plan, so that a slot costs
+// one global load (its value), one 2-byte load (its target index) and one
+// store. About 35 KB plus 80 bytes per type: four 512-thread workgroups of a
 // plan with up to a dozen types fit one CU's 160 KB.
 struct RelocLds {
-  uint64_t keys[kSegHashSlots];
-  uint64_t vals[kSegHashSlots];
+  uint64_t from[kSegMaxSlots];     // a target's address before the translation
+  uint64_t to[kSegMaxSlots];       // and after it
   uint64_t sobj[kSegMaxSObjs];     // arena offset | type << 56
   uint32_t rel[kSegMaxSObjs + 4];  // slot prefix - first slot, clamped to [0, slots of the unit]
   // RelocType types[ntypes] follows
@@ -63,39 +96,6 @@ static_assert(sizeof(RelocLds) % 16 == 0, "types start 16-byte aligned");
 
 __host__ __device__ constexpr size_t reloc_lds_bytes(uint32_t ntypes) {
   return sizeof(RelocLds) + (size_t)ntypes * sizeof(RelocType);
-}
-
-__device__ __forceinline__ uint32_t hash_slot(uint64_t key) {
-  // multiplicative hashing; keys are 16-byte aligned addresses
-  return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - 10)) & (kSegHashSlots - 1);
-}
-static_assert(kSegHashSlots == 1024, "hash_slot assumes 2^10 slots");
-
-__device__ __forceinline__ void hash_insert(uint64_t* keys, uint64_t* vals, uint64_t key, uint64_t val) {
-  uint32_t h = hash_slot(key);
-  for (uint32_t probe = 0; probe < kSegHashSlots; probe++) {
-    unsigned long long prev = atomicCAS((unsigned long long*)&keys[h], 0ull, (unsigned long long)key);
-    if (prev == 0ull || prev == key) {
-      vals[h] = val;
-      return;
-    }
-    h = (h + 1) & (kSegHashSlots - 1);
-  }
-}
-
-// the translated value of key, or false if key is not one of the unit's targets
-__device__ __forceinline__ bool hash_find(const uint64_t* keys, const uint64_t* vals, uint64_t key, uint64_t* val) {
-  uint32_t h = hash_slot(key);
-  for (uint32_t probe = 0; probe < kSegHashSlots; probe++) {
-    uint64_t k = keys[h];
-    if (k == key) {
-      *val = vals[h];
-      return true;
-    }
-    if (k == 0) return false;
-    h = (h + 1) & (kSegHashSlots - 1);
-  }
-  return false;
 }
 
 __device__ __forceinline__ void report_bad_slot(DevHeader* hdr, uint64_t slot_off) {
@@ -118,20 +118,19 @@ __device__ __noinline__ void report_wild(DevHeader* hdr) {
 }
 
 // Translates every pointer slot of relocation unit `sg`. attach: host address
-// -> arena address; detach: arena address -> host address. A slot holding a
-// value that is not one of the unit's planned targets is left alone and
+// -> arena address; detach: arena address -> host address. A slot must hold
+// its planned target's address (or null): any other value is left alone and
 // reported in the header. Three dependent rounds of global accesses: the
-// unit's tables; the slots' current values together with the targets'
-// translations; the translated stores. A unit's at most 1024 slots are KS per
-// thread: four for 256 threads, two for 512, one for 1024.
-static_assert(kSegMaxSlots <= 4 * 256, "four slots per thread of a 256-thread workgroup");
+// unit's tables, targets and the slots' target indices; the slots' current
+// values; the translated stores. A unit's at most 2048 slots are KS per
+// thread (bs * KS >= 2048).
 
 // A slot the unit translated, kept by a caller that restores it later: its
-// arena offset (kKeepBad set when its value was not a planned target, ~0 for
-// none) and its value before the translation.
+// arena offset (kKeepBad set when its value was not its planned target, ~0
+// for none) and its value before the translation.
 constexpr uint64_t kKeepBad = 1ull << 63;
 
-template <bool KEEP, int KS = 4>
+template <bool KEEP, int KS>
 __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t* lds, uint64_t* keep_off = nullptr,
                               uint64_t* keep_val = nullptr) {
   RelocLds* L = (RelocLds*)lds;
@@ -143,8 +142,21 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
   // slot prefix of the unit's first struct array, which may begin before the unit
   const uint64_t pre0 = t.sobj_pre[seg.sobj_lo];
 
-  // stage: the unit's struct arrays and slot prefix, and the types
-  for (uint32_t i = tid; i < kSegHashSlots; i += bs) L->keys[i] = 0;
+  // the target index of each of the thread's slots, loaded with the tables
+  uint32_t tx[KS];
+#pragma unroll
+  for (int k = 0; k < KS; k++) {
+    const uint32_t jr = (uint32_t)k * bs + tid;
+    tx[k] = jr < nslots ? t.slot_tix[seg.slot_lo + jr] : kNoTarget;
+  }
+  // stage: the targets' translations, the unit's struct arrays and slot
+  // prefix, and the types
+  const uint32_t ntgt = (uint32_t)(seg.tgt_hi - seg.tgt_lo);
+  for (uint32_t i = tid; i < ntgt; i += bs) {
+    const DevTarget tg = t.tgts[seg.tgt_lo + i];
+    L->from[i] = attach ? tg.host : B + tg.off;
+    L->to[i] = attach ? B + tg.off : tg.host;
+  }
   const uint32_t nso = seg.sobj_hi - seg.sobj_lo;
   for (uint32_t i = tid; i <= nso; i += bs) {
     const uint64_t pr = t.sobj_pre[seg.sobj_lo + i];
@@ -164,8 +176,7 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
   }
   lds_barrier();
 
-  // the thread's slots (at most KS, with bs * KS >= kSegMaxSlots): their
-  // arena offsets and current values
+  // the thread's slots: their arena offsets and current values
   uint64_t soff[KS], val[KS];
   bool fol[KS];
 #pragma unroll
@@ -191,14 +202,6 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
     fol[k] = (ty.follow >> f) & 1u;
     val[k] = *(const g_u64*)(B + soff[k]);
   }
-  // the translation of every target (host address <-> arena address), loaded
-  // while the slot values are in flight
-  const uint32_t ntgt = (uint32_t)(seg.tgt_hi - seg.tgt_lo);
-  for (uint32_t i = tid; i < ntgt; i += bs) {
-    const DevTarget tg = t.tgts[seg.tgt_lo + i];
-    hash_insert(L->keys, L->vals, attach ? tg.host : B + tg.off, attach ? B + tg.off : tg.host);
-  }
-  lds_barrier();
 
 #pragma unroll
   for (int k = 0; k < KS; k++) {
@@ -209,13 +212,12 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
       *(g_u64*)(B + soff[k]) = 0;
       continue;
     }
-    uint64_t nv;
-    if (!hash_find(L->keys, L->vals, val[k], &nv)) {
+    if (tx[k] >= ntgt || L->from[tx[k]] != val[k]) {
       report_bad_slot(t.hdr, soff[k]);
       if (KEEP) keep_off[k] = soff[k] | kKeepBad;
       continue;
     }
-    *(g_u64*)(B + soff[k]) = nv;
+    *(g_u64*)(B + soff[k]) = L->to[tx[k]];
     if (KEEP) {
       keep_off[k] = soff[k];
       keep_val[k] = val[k];
@@ -223,10 +225,10 @@ __device__ void relocate_unit(const Tables& t, uint64_t sg, bool attach, uint8_t
   }
 }
 
-__global__ void __launch_bounds__(kRelocBlock, 8) k_relocate(Tables t, int attach) {
+__global__ void __launch_bounds__(kRelocBlock, 4) k_relocate(Tables t, int attach) {
   extern __shared__ __align__(16) uint8_t lds[];
   for (uint64_t sg = blockIdx.x; sg < t.nseg; sg += gridDim.x) {
-    relocate_unit<false>(t, sg, attach != 0, lds);
+    relocate_unit<false, kSegMaxSlots / kRelocBlock>(t, sg, attach != 0, lds);
     lds_barrier();
   }
 }
@@ -385,7 +387,7 @@ __device__ __forceinline__ const uint8_t* opaque(const uint8_t* p) {
 
 // ---- one array at the end of a resolved chain ----------------------------------------------
 
-template <int U, typename T>
+template <int U, typename T, bool NT>
 __global__ void __launch_bounds__(256) k_stream_resolved(Tables t, uint64_t base, uint64_t count, LeafArgs la) {
   const uint64_t bytes = count * sizeof(T);
   if (!in_arena(t, base, bytes)) {
@@ -401,14 +403,14 @@ __global__ void __launch_bounds__(256) k_stream_resolved(Tables t, uint64_t base
 #pragma unroll
     for (int k = 0; k < U; k++) {
       const uint64_t c = c0 + (uint64_t)k * blockDim.x;
-      if (c < nfull) v[k].u = gload16(src + c * kChunk);
+      if (c < nfull) v[k].u = sload16<NT>(src + c * kChunk);
     }
 #pragma unroll
     for (int k = 0; k < U; k++) {
       const uint64_t c = c0 + (uint64_t)k * blockDim.x;
       if (c < nfull) {
         fma_chunk_t<T>(v[k], la);
-        gstore16(dst + c * kChunk, v[k].u);
+        sstore16<NT>(dst + c * kChunk, v[k].u);
       }
     }
   }
@@ -442,7 +444,7 @@ __device__ __forceinline__ uint64_t walk_load(uint64_t addr) {
 // while the walk runs, and must land on the checked address. Checking every
 // hop of every walk instead puts a vector compare on the scalar load chain
 // and costs about a fifth of the bandwidth.
-template <int U, int MAXH, typename T>
+template <int U, int MAXH, typename T, bool NT>
 __global__ void __launch_bounds__(256) k_stream_deref(Tables t, HopArgs h, uint64_t count, LeafArgs la) {
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
   const uint32_t lane = threadIdx.x & 63;
@@ -488,15 +490,15 @@ __global__ void __launch_bounds__(256) k_stream_deref(Tables t, HopArgs h, uint6
   for (int k = 0; k < U; k++) {
     const uint64_t i = i0 + (uint64_t)k * 64;
     const uint64_t src = la.src_out ? (uint64_t)la.out : p[k];
-    if (i < count) x[k] = *(const __attribute__((address_space(1))) T*)(src + i * sizeof(T));
+    if (i < count) x[k] = sload<NT, T>(src + i * sizeof(T));
   }
 #pragma unroll
   for (int k = 0; k < U; k++) {
     const uint64_t i = i0 + (uint64_t)k * 64;
     const uint64_t dst = (la.out ? (uint64_t)la.out : p[k]) + i * sizeof(T);
     if (i < count) {
-      if constexpr (sizeof(T) == 8) *(g_double*)dst = __builtin_fma(x[k], la.a, la.b);
-      else *(g_float*)dst = __builtin_fmaf(x[k], la.af, la.bf);
+      if constexpr (sizeof(T) == 8) sstore<NT, double>(dst, __builtin_fma(x[k], la.a, la.b));
+      else sstore<NT, float>(dst, __builtin_fmaf(x[k], la.af, la.bf));
     }
   }
 }
@@ -636,7 +638,7 @@ __global__ void __launch_bounds__(256) k_leaf_tiles(Tables t, LeafArgs la, uint6
 // checked against the arena; per chunk: v = fma(f, dt/m, v), x = fma(v, dt, x).
 constexpr size_t kKdLds = (size_t)(kTileMaxLeaves + 2) * 5 * 8;
 
-template <int U>
+template <int U, bool NT>
 __global__ void __launch_bounds__(256) k_kick_drift(Tables t, KickDriftArgs k) {
   __shared__ __align__(16) uint8_t lds[kKdLds];
   constexpr uint32_t N = kTileMaxLeaves + 2;
@@ -683,9 +685,9 @@ __global__ void __launch_bounds__(256) k_kick_drift(Tables t, KickDriftArgs k) {
           xd[u] = xa[i] + e * 8;
           vd[u] = va[i] + e * 8;
           if (ne[u] == 2) {
-            X[u].u = gload16(xd[u]);
-            V[u].u = gload16(vd[u]);
-            F[u].u = gload16(fa[i] + e * 8);
+            X[u].u = sload16<NT>(xd[u]);
+            V[u].u = sload16<NT>(vd[u]);
+            F[u].u = sload16<NT>(fa[i] + e * 8);
           } else if (ne[u] == 1) {
             X[u].d[0] = *(const g_double*)xd[u];
             V[u].d[0] = *(const g_double*)vd[u];
@@ -700,8 +702,8 @@ __global__ void __launch_bounds__(256) k_kick_drift(Tables t, KickDriftArgs k) {
           V[u].d[1] = __builtin_fma(F[u].d[1], k.dt_over_m, V[u].d[1]);
           X[u].d[0] = __builtin_fma(V[u].d[0], k.dt, X[u].d[0]);
           X[u].d[1] = __builtin_fma(V[u].d[1], k.dt, X[u].d[1]);
-          gstore16(vd[u], V[u].u);
-          gstore16(xd[u], X[u].u);
+          sstore16<NT>(vd[u], V[u].u);
+          sstore16<NT>(xd[u], X[u].u);
         } else if (ne[u] == 1) {
           const double v1 = __builtin_fma(F[u].d[0], k.dt_over_m, V[u].d[0]);
           *(g_double*)vd[u] = v1;
@@ -770,6 +772,7 @@ __device__ __forceinline__ void report_done(uint32_t* ctr, uint32_t n, bool rele
 template <int U, int BS>
 __global__ void __launch_bounds__(BS, 8) k_batch(Tables t, LeafArgs la, uint32_t flags, uint64_t ntiles,
                                                   uint32_t per_item, uint32_t spin_limit) {
+  constexpr int KS = (int)((kSegMaxSlots + BS - 1) / BS);
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ uint32_t s_item;
   DevHeader* hdr = t.hdr;
@@ -797,7 +800,7 @@ __global__ void __launch_bounds__(BS, 8) k_batch(Tables t, LeafArgs la, uint32_t
     }
     if (item >= total) break;
     if (item < nA) {
-      relocate_unit<false>(t, item, true, lds);
+      relocate_unit<false, KS>(t, item, true, lds);
       lds_barrier();
       myA++;
     } else if (item < nA + nB) {
@@ -811,7 +814,7 @@ __global__ void __launch_bounds__(BS, 8) k_batch(Tables t, LeafArgs la, uint32_t
         wait_count(hdr, &hdr->doneB, nB + extra, spin_limit);
         waitedB = true;
       }
-      relocate_unit<false>(t, item - nA - nB, false, lds);
+      relocate_unit<false, KS>(t, item - nA - nB, false, lds);
       lds_barrier();
     }
   }
@@ -959,6 +962,13 @@ hipError_t launch_relocate(const Tables& t, bool attach, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Streams of at least this many bytes per pass use non-temporal accesses:
+// larger than the 256 MB Infinity Cache, they are not read again from it.
+#ifndef DC_STREAM_NT_BYTES
+#define DC_STREAM_NT_BYTES (256ull << 20)
+#endif
+static bool stream_nt(uint64_t bytes) { return bytes >= (uint64_t)DC_STREAM_NT_BYTES; }
+
 hipError_t launch_scalar(const Tables& t, const DevScalar* refs, const DevScalarHop* hops, uint32_t n,
                          uint64_t* temps, int update, hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -973,7 +983,11 @@ hipError_t launch_kick_drift(const Tables& t, const KickDriftArgs& k, hipStream_
   // 10,000 MD simulations (19.8 GB per step) 3.86 ms, against 4.07 ms with two
   // chunks per thread at five workgroups per CU (4.47 at eight) and 4.3-4.7 ms
   // with four
-  hipLaunchKernelGGL(k_kick_drift<1>, dim3((uint32_t)grid), dim3(256), 0, s, t, k);
+  // the three arrays of every element are leaves of the tree: its leaf bytes decide
+  if (stream_nt(t.total_chunks * kChunk))
+    hipLaunchKernelGGL((k_kick_drift<1, true>), dim3((uint32_t)grid), dim3(256), 0, s, t, k);
+  else
+    hipLaunchKernelGGL((k_kick_drift<1, false>), dim3((uint32_t)grid), dim3(256), 0, s, t, k);
   return hipGetLastError();
 }
 
@@ -994,10 +1008,15 @@ hipError_t launch_stream_resolved(const Tables& t, uint64_t base, uint64_t count
   uint64_t blocks = (chunks + 256ull * U - 1) / (256ull * U);
   if (blocks > (1ull << 31) - 1) blocks = (1ull << 31) - 1;
   if (blocks == 0) blocks = 1;
-  if (kind == DC_KIND_F64)
-    hipLaunchKernelGGL((k_stream_resolved<U, double>), dim3((uint32_t)blocks), dim3(256), 0, s, t, base, count, la);
+  const bool nt = stream_nt(bytes);
+  if (kind == DC_KIND_F64 && nt)
+    hipLaunchKernelGGL((k_stream_resolved<U, double, true>), dim3((uint32_t)blocks), dim3(256), 0, s, t, base, count, la);
+  else if (kind == DC_KIND_F64)
+    hipLaunchKernelGGL((k_stream_resolved<U, double, false>), dim3((uint32_t)blocks), dim3(256), 0, s, t, base, count, la);
+  else if (nt)
+    hipLaunchKernelGGL((k_stream_resolved<U, float, true>), dim3((uint32_t)blocks), dim3(256), 0, s, t, base, count, la);
   else
-    hipLaunchKernelGGL((k_stream_resolved<U, float>), dim3((uint32_t)blocks), dim3(256), 0, s, t, base, count, la);
+    hipLaunchKernelGGL((k_stream_resolved<U, float, false>), dim3((uint32_t)blocks), dim3(256), 0, s, t, base, count, la);
   return hipGetLastError();
 }
 
@@ -1007,11 +1026,18 @@ hipError_t launch_stream_deref(const Tables& t, const HopArgs& h, uint64_t count
   const uint64_t blocks = (count + 256ull * U - 1) / (256ull * U);
   if (blocks == 0) return hipSuccess;
   if (h.nhops > kMaxChainSteps) return hipErrorInvalidValue;
-#define DC_DEREF(MAXH)                                                                                     \
-  if (kind == DC_KIND_F64)                                                                                 \
-    hipLaunchKernelGGL((k_stream_deref<U, MAXH, double>), dim3((uint32_t)blocks), dim3(256), 0, s, t, h, count, la); \
-  else                                                                                                     \
-    hipLaunchKernelGGL((k_stream_deref<U, MAXH, float>), dim3((uint32_t)blocks), dim3(256), 0, s, t, h, count, la);
+  const bool nt = stream_nt(count * (kind == DC_KIND_F64 ? 8 : 4));
+#define DC_DEREF_T(MAXH, T)                                                                                          \
+  if (nt)                                                                                                            \
+    hipLaunchKernelGGL((k_stream_deref<U, MAXH, T, true>), dim3((uint32_t)blocks), dim3(256), 0, s, t, h, count, la);  \
+  else                                                                                                               \
+    hipLaunchKernelGGL((k_stream_deref<U, MAXH, T, false>), dim3((uint32_t)blocks), dim3(256), 0, s, t, h, count, la);
+#define DC_DEREF(MAXH)       \
+  if (kind == DC_KIND_F64) { \
+    DC_DEREF_T(MAXH, double) \
+  } else {                   \
+    DC_DEREF_T(MAXH, float)  \
+  }
   if (h.nhops <= 4) {
     DC_DEREF(4)
   } else if (h.nhops <= 8) {
@@ -1022,6 +1048,7 @@ hipError_t launch_stream_deref(const Tables& t, const HopArgs& h, uint64_t count
     DC_DEREF(32)
   }
 #undef DC_DEREF
+#undef DC_DEREF_T
   return hipGetLastError();
 }
 
@@ -1031,6 +1058,8 @@ hipError_t launch_leaf_tiles(const Tables& t, const LeafArgs& la, uint64_t ntile
   const uint64_t grid = ntiles < (1u << 20) ? ntiles : (1u << 20);
   // RESOLVED: one round per tile for 512- and 1024-chunk tiles (two or four
   // chunks per thread), rounds of 1024 for larger ones
+  // (the sweep of chunks per thread x non-temporal accesses on the MD leaves,
+  // best tile size each: 1 chunk 4.46 ms, 2 4.44, 4 4.25; non-temporal 4.72-4.95)
   if (deref_each)
     hipLaunchKernelGGL((k_leaf_tiles<4, true>), dim3((uint32_t)grid), dim3(256), 0, s, t, la, ntiles);
   else if (tile_chunks <= 512)

@@ -525,6 +525,8 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     uint64_t unit_slots = 128;
     while (unit_slots < kSegMaxSlots && nslots / unit_slots > 256) unit_slots *= 2;
     bigvec<uint32_t> mark(nobj);
+    bigvec<uint16_t> tix(nobj);  // index of an object in the current unit's targets
+    p->slot_tix.resize(nslots);
     std::vector<std::vector<DevSeg>> csegs(nch);
     std::vector<std::vector<DevTarget>> ctgts(nch);
     each_chunk([&](int c) {
@@ -556,17 +558,24 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
           open(p->sobj_pre[so], so);
         }
         for (uint64_t j = p->sobj_pre[so]; j < p->sobj_pre[so + 1]; j++) {
-          const uint32_t t = p->slot_target[j];
-          const bool new_tgt = t != kNone && mark[t] != seg_id;
-          if (j - cur.slot_lo >= unit_slots || (new_tgt && ntgt == kSegMaxTargets)) {
+          // a unit's distinct targets never outnumber its slots: the slot
+          // count alone bounds the target list and its 16-bit indices
+          if (j - cur.slot_lo >= unit_slots) {
             close(j, so + 1);
             open(j, so);
           }
-          if (t != kNone && mark[t] != seg_id) {
+          const uint32_t t = p->slot_target[j];
+          if (t == kNone) {
+            p->slot_tix[j] = kNoTarget;
+            continue;
+          }
+          if (mark[t] != seg_id) {
             mark[t] = seg_id;
+            tix[t] = (uint16_t)ntgt;
             tgts.push_back(DevTarget{p->objs[t].host, p->objs[t].off});
             ntgt++;
           }
+          p->slot_tix[j] = tix[t];
         }
       }
       close(cslot[c + 1], csobj[c + 1]);
@@ -735,6 +744,7 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     s.sobj_pre = take(8 * p->sobj_pre.size());
     s.segs = take(sizeof(DevSeg) * p->segs.size());
     s.tgts = take(sizeof(DevTarget) * p->tgts.size());
+    s.slot_tix = take(2 * p->slot_tix.size());
     s.leaf_slot = take(8 * nl);
     s.leaf_pre = take(8 * (nl + 1));
     s.leaf_info = take(8 * nl);

@@ -17,6 +17,7 @@ static Tables make_tables(dc_plan p, uint8_t* arena, uint8_t* scratch) {
   t.sobj_pre = (const uint64_t*)(scratch + s.sobj_pre);
   t.segs = (const DevSeg*)(scratch + s.segs);
   t.tgts = (const DevTarget*)(scratch + s.tgts);
+  t.slot_tix = (const uint16_t*)(scratch + s.slot_tix);
   t.leaf_slot = (const uint64_t*)(scratch + s.leaf_slot);
   t.leaf_pre = (const uint64_t*)(scratch + s.leaf_pre);
   t.leaf_info = (const uint64_t*)(scratch + s.leaf_info);
@@ -71,6 +72,7 @@ static dc_status upload_tables(dc_ctx ctx, dc_plan p, uint8_t* arena, uint8_t* s
   add(sl.sobj_pre, p->sobj_pre.data(), 8 * p->sobj_pre.size());
   add(sl.segs, p->segs.data(), sizeof(DevSeg) * p->segs.size());
   add(sl.tgts, p->tgts.data(), sizeof(DevTarget) * p->tgts.size());
+  add(sl.slot_tix, p->slot_tix.data(), 2 * p->slot_tix.size());
   add(sl.leaf_slot, p->leaf_slot.data(), 8 * p->leaf_slot.size());
   add(sl.leaf_pre, p->leaf_pre.data(), 8 * p->leaf_pre.size());
   add(sl.leaf_info, p->leaf_info.data(), 8 * p->leaf_info.size());
