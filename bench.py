@@ -37,9 +37,10 @@ LINK_WARMUP, LINK_REPS = 2, 5   # untimed, then timed deep copies of the host-li
 
 
 def traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` measured by rocprofv3 counters
-    (profiles/hbm_counters.txt), or None when there is no entry or the
-    kernel source has changed since the counters were taken."""
+    """L2-to-fabric bytes per launch of `kernel` (Infinity Cache hits and HBM
+    together) measured by rocprofv3 counters (profiles/hbm_counters.txt), or
+    None when there is no entry or the kernel source has changed since the
+    counters were taken."""
     import hashlib
     try:
         src = open(os.path.join(ROOT, "paper_1906_01128_amd", "csrc", "dc_kernels.hip"), "rb").read()
@@ -729,6 +730,7 @@ def _batched_secondary(args, torch, dc, ctx, t, plan, tree, info, table):
             "relocation": {"kernel": "k_relocate", "attach_us": round(1e6 * att_s, 1), "detach_us": round(1e6 * det_s, 1),
                            "bytes_per_launch": rel_bytes, "achieved_GBps": round(rel_bytes / att_s / 1e9, 1),
                            "frac": round(rel_bytes / att_s / 1e9 / HBM_PEAK_GBPS, 4),
+                           "traffic": traffic("batched", "k_relocate"),
                            "bytes": "8 B read + 8 B written per non-null slot, 8 B read per null slot, 16 B per "
                                     "object (its target entry); the 2-byte target index per slot is not counted"},
             "kick_drift": {"kernel": "k_kick_drift", "ms": round(1e3 * pct(kd, 50), 3),
@@ -975,13 +977,16 @@ def bench_sweep(args, torch, dc):
 
 
 def bench_copycal(args, torch, dc):
-    """A plain device-to-device copy of 1 GiB, three times: the reference
-    kernel whose FETCH_SIZE / WRITE_SIZE counters calibrate the HBM traffic
-    counters of the other kernels (it reads and writes exactly 2^30 bytes)."""
+    """Reference kernels of known traffic whose FETCH_SIZE / WRITE_SIZE
+    counters calibrate those of the other kernels: a plain device-to-device
+    copy of 1 GiB (reads and writes exactly 2^30 bytes), three times, and an
+    in-place multiply of 1 GiB of nonzero doubles (reads and writes the same
+    2^30 bytes, as the leaf kernels do), three times."""
     n = 1 << 30
     a = torch.empty(n, dtype=torch.uint8, device="cuda")
     b = torch.empty(n, dtype=torch.uint8, device="cuda")
     a.fill_(1)
+    x = torch.rand(n // 8, dtype=torch.float64, device="cuda").add_(0.5)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -991,8 +996,16 @@ def bench_copycal(args, torch, dc):
     e1.record(s)
     e1.synchronize()
     t = e0.elapsed_time(e1) / 1e3 / 3
+    e0.record(s)
+    for _ in range(3):
+        x.mul_(1.0000001)
+    e1.record(s)
+    e1.synchronize()
+    tm = e0.elapsed_time(e1) / 1e3 / 3
     return {"metric": "device copy GB/s (counter calibration)", "value": round(2 * n / t / 1e9, 1), "unit": "GB/s",
-            "config": {"workload": "copy 2^30 bytes device to device, 3 times"}}
+            "config": {"workload": "copy 2^30 bytes device to device, 3 times; in-place multiply of 2^30 bytes of "
+                                   "doubles, 3 times"},
+            "inplace_multiply_GBps": round(2 * n / tm / 1e9, 1)}
 
 
 def main():
