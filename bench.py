@@ -126,7 +126,9 @@ def cpu_baseline_linear(args, passes):
     kernel_bytes = 2 * 2 * leaf * passes
     return {"value": round(kernel_bytes / (t2 - t1) / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"linear chain k=8, 2^24 FP64: deep copy, {passes} fma passes x 2 modes, copy back; "
-                      f"kernel GB/s over the passes (deep copy {t1 - t0:.3f} s, copy back {t3 - t2:.3f} s)",
+                      f"credited with the GPU passes' bytes (2 x leaf per pass), although the oracle keeps each "
+                      f"element in a register across its passes and moves the leaf once per run: an fma-latency "
+                      f"rate, not memory bandwidth (deep copy {t1 - t0:.3f} s, copy back {t3 - t2:.3f} s)",
             "seconds": round(t3 - t0, 3)}
 
 
