@@ -596,7 +596,8 @@ def bench_batched(args, torch, dc):
     form = {0: "one persistent launch, one relocation unit per item" if info.unit_leaves else
                "one persistent launch in three phases",
             1: "three launches (relocate, every leaf, reverse relocate)",
-            2: "one persistent launch in three phases"}[tune["launches"]]
+            2: "one persistent launch in three phases",
+            3: "one fused launch: every tile relocates the slots of its own leaves"}[tune["launches"]]
     if tune["launches"] == 1:
         # the compute launch of the graph, timed as separate launches
         kname, kbytes = "k_leaf_tiles", 2 * info.leaf_bytes
@@ -613,6 +614,20 @@ def bench_batched(args, torch, dc):
         tree.detach()
         k_s = sum(ks) / len(ks)
         k_what = "k_leaf_tiles timed as separate launches beside the graph"
+    elif tune["launches"] == 3:
+        # the graph's one launch, timed as separate launches of the same form
+        kname, kbytes = "k_fused", step_bytes
+        tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=tune)
+        ks = []
+        for _ in range(5):
+            e = _events(torch, 2)
+            e[0].record(s)
+            tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=tune)
+            e[1].record(s)
+            torch.cuda.synchronize()
+            ks.append(e[0].elapsed_time(e[1]) / 1e3)
+        k_s = sum(ks) / len(ks)
+        k_what = "k_fused (relocation and compute in one launch) timed as separate launches beside the graph"
     else:
         kname = "k_batch_units" if (tune["launches"] == 0 and info.unit_leaves) else "k_batch"
         kbytes, k_s = step_bytes, mean_s
@@ -695,7 +710,7 @@ def _batched_secondary(args, torch, dc, ctx, t, plan, tree, info, table):
     best = {}
     for tu, us in table:
         key = {0: "persistent_units" if info.unit_leaves else "persistent_phased", 1: "three_launches",
-               2: "persistent_phased"}[tu["launches"]]
+               2: "persistent_phased", 3: "fused"}[tu["launches"]]
         if key not in best or us < best[key]["us"]:
             best[key] = dict(tu, us=round(us, 1), GBps=round(step_bytes / us / 1e3, 1))
     # attach and detach alone (the relocation kernel), medians of 5
@@ -810,6 +825,17 @@ def bench_served(args, torch, dc, budget=200 * 10 ** 9):
                 "h2d_GBps": round(st.h2d_bytes / wall / 1e9, 2), "d2h_GBps": round(st.d2h_bytes / wall / 1e9, 2),
                 "busier_direction_frac_of_measured": round(max(st.h2d_bytes, st.d2h_bytes) / wall / cap, 4),
                 "busier_direction_frac_of_spec": round(max(st.h2d_bytes, st.d2h_bytes) / wall / 1e9 / LINK_PEAK_GBPS, 4)}
+    # the same jobs at capacity with page-locked output buffers, which the
+    # server fills by direct copies from the device
+    outs_pinned = [torch.zeros(max(sz[1], 1), dtype=torch.uint8, pin_memory=True).numpy() for sz in sizes]
+    _, stp, wallp = _served_run(dc, ctx, schema, pool, sizes, jobs, outs_pinned, 0, budget)
+    del outs_pinned
+    capacity["pinned_outputs"] = {
+        "wall_s": round(wallp, 3), "jobs_per_s": round(njobs / wallp, 1),
+        "h2d_GBps": round(stp.h2d_bytes / wallp / 1e9, 2), "d2h_GBps": round(stp.d2h_bytes / wallp / 1e9, 2),
+        "busier_direction_frac_of_measured": round(max(stp.h2d_bytes, stp.d2h_bytes) / wallp / cap, 4),
+        "busier_direction_frac_of_spec": round(max(stp.h2d_bytes, stp.d2h_bytes) / wallp / 1e9 / LINK_PEAK_GBPS, 4)}
+    log(args, f"served capacity, pinned outputs: {njobs / wallp:.1f} jobs/s ({wallp:.2f} s)")
     # the plain path: one structure per call, back to back, no residency
     plain_lat = []
     t0 = time.perf_counter()

@@ -412,7 +412,9 @@ typedef struct {
                               (relocate, every leaf, reverse relocate), for which
                               block and wg_per_cu are not used; 2: one persistent
                               launch in three phases (what 0 runs when the plan's
-                              relocation units do not own contiguous leaf runs) */
+                              relocation units do not own contiguous leaf runs);
+                              3: one fused launch of tiles that relocate their own
+                              leaves' slots (block and wg_per_cu not used) */
   uint32_t spin_limit;     /* persistent launch: polls (about 1 us each) a workgroup
                               waits for a phase to finish before it records an error
                               and goes on, so that every launch ends; 0: 2^24 */
@@ -423,7 +425,7 @@ typedef struct {
  * than its phase has, so each wait ends at its bound (keep tune->spin_limit
  * small); the launch still ends, the tree's leaf values and slots are then
  * unspecified, and the next check of the tree returns DC_E_STATE. DC_E_INVAL
- * with three launches. */
+ * with three launches or the fused launch (no waits to force). */
 enum { DC_BATCH_ATTACH = 1, DC_BATCH_DETACH = 2, DC_BATCH_FORCE_WAIT_BOUND = 4 };
 /* Every structure's relocation and its leaves' kernel (args: RESOLVED,
  * ALL_LEAVES, iters == 1), the batched use of Figure 2(d) and Algorithm 2
@@ -435,7 +437,15 @@ enum { DC_BATCH_ATTACH = 1, DC_BATCH_DETACH = 2, DC_BATCH_FORCE_WAIT_BOUND = 4 }
  * and its detach, with no wait between workgroups. Otherwise the launch runs
  * in three phases: attach units, then compute tiles, then (DETACH) reverse
  * relocation units, each phase waiting for the one before. 2: always the
- * three phases. 1: the same work as three stream-ordered launches. ATTACH
+ * three phases. 1: the same work as three stream-ordered launches. 3: one
+ * launch over the compute tiles in which every tile translates the slot each
+ * of its leaves was first reached through (the tile holding the leaf's first
+ * chunk checks it and, after its compute, attaches and then detaches it as the
+ * flags ask; a tile holding later chunks of the same leaf accepts either value;
+ * every tile computes at the leaf's planned address, the value the attach
+ * writes), and
+ * workgroups past the tiles translate every other slot; no workgroup waits for
+ * another, and any plan can use it. ATTACH
  * requires a staged (unrelocated) tree; DETACH leaves it staged again. tune
  * NULL: the cached autotuner choice or defaults. Asynchronous on `stream`. */
 dc_status dc_batch_run(dc_tree tree, const dc_kernel_args* args, const dc_tune* tune, uint32_t flags, void* stream);
@@ -500,7 +510,9 @@ typedef struct {
                               unchanged structure; 0 = never reuse */
   double a, b;             /* the job's kernel: out = fma(leaf, a, b) */
   float af, bf;
-  void* out_host;          /* host buffer receiving the leaf image */
+  void* out_host;          /* host buffer receiving the leaf image; when it is
+                              page-locked (hipHostMalloc) each leaf is copied
+                              into it directly, else through pinned staging */
   uint64_t out_bytes;      /* its size; must be >= the structure's leaf image */
 } dc_request;
 

@@ -22,7 +22,7 @@ static const dc_tune kDefaultTune = {256, 4, 1024, 1, 0};
 static const uint32_t kDefaultSpin = 1u << 24;  // polls of a persistent workgroup's wait
 
 static dc_status check_tune(const dc_tune& t) {
-  if (t.launches > 2) return fail(DC_E_INVAL, "tune.launches %u (0, 1 or 2)", t.launches);
+  if (t.launches > 3) return fail(DC_E_INVAL, "tune.launches %u (0, 1, 2 or 3)", t.launches);
   if (t.block != 256 && t.block != 512 && t.block != 1024) return fail(DC_E_INVAL, "tune.block %u", t.block);
   if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return fail(DC_E_INVAL, "tune.wg_per_cu %u", t.wg_per_cu);
   if (t.tile_chunks < kTileMinChunks || t.tile_chunks > kTileMaxChunks || (t.tile_chunks & (t.tile_chunks - 1)))
@@ -146,6 +146,9 @@ static dc_status enqueue_batch(dc_tree t, const LeafArgs& la, const dc_tune& tu,
     if (flags & DC_BATCH_ATTACH) e = launch_relocate(t->tab, true, s);
     if (e == hipSuccess) e = launch_leaf_tiles(t->tab, la, ntiles, t->tile_T, false, s);
     if (e == hipSuccess && (flags & DC_BATCH_DETACH)) e = launch_relocate(t->tab, false, s);
+  } else if (tu.launches == 3) {
+    // one launch: every tile relocates the slots of its own leaves
+    e = launch_fused(t->tab, la, ntiles, t->tile_T, flags & (DC_BATCH_ATTACH | DC_BATCH_DETACH), s);
   } else if (unit_items(t, tu, flags)) {
     e = launch_reset_counters(t->tab.hdr, s);
     if (e == hipSuccess) e = launch_batch_units(t->tab, la, flags, tu.block, grid, s);
@@ -188,8 +191,8 @@ dc_status dc_batch_run(dc_tree t, const dc_kernel_args* a, const dc_tune* tune, 
   DC_TRY(batch_args(t, a, &la));
   dc_tune tu;
   DC_TRY(resolve_tune(t, tune, &tu));
-  if ((flags & DC_BATCH_FORCE_WAIT_BOUND) && tu.launches == 1)
-    return fail(DC_E_INVAL, "FORCE_WAIT_BOUND needs a persistent launch (tune.launches 0 or 2)");
+  if ((flags & DC_BATCH_FORCE_WAIT_BOUND) && (tu.launches == 1 || tu.launches == 3))
+    return fail(DC_E_INVAL, "FORCE_WAIT_BOUND needs a launch with waits (tune.launches 0 or 2)");
   DC_HIP(hipSetDevice(t->ctx->device));
   DC_TRY(enqueue_batch(t, la, tu, flags, (hipStream_t)stream));
   if (flags & DC_BATCH_DETACH) t->attached = false;
@@ -231,6 +234,7 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
         if (block * wg >= 1024) cands.push_back(dc_tune{block, wg, tile, phased, 0});
     }
   for (uint32_t tile : {512u, 1024u, 2048u, 4096u}) cands.push_back(dc_tune{256, 1, tile, 1, 0});
+  for (uint32_t tile : {512u, 1024u, 2048u}) cands.push_back(dc_tune{256, 1, tile, 3, 0});
   clear_error();
   t->tune_table.clear();
   dc_tune best = kDefaultTune;

@@ -80,6 +80,15 @@ struct DevSeg {
 // info = bytes | kind << 56.
 constexpr int kLeafKindShift = 56;
 
+// A pointer slot the fused relocate-and-compute launch translates on its own:
+// one that is not the discovering slot of a leaf (null, unfollowed, reaching
+// a struct, integer or empty array, or a second reach of any array).
+struct DevResid {
+  uint64_t slot_off;  // arena offset of the slot
+  uint32_t tgt;       // global index of its target entry, kNone for a null slot
+  uint32_t follow;    // 0: a member left out of a selective copy (zeroed)
+};
+
 struct DevPath {  // pointer path by which the walk first reached a leaf
   uint64_t root_off;
   uint32_t hop_lo, nhops;
@@ -123,7 +132,7 @@ enum DevErr : uint32_t {
 
 struct ScratchLayout {
   uint64_t header, types, sobj, sobj_pre, segs, tgts, slot_tix;
-  uint64_t leaf_slot, leaf_pre, leaf_info, leaf_out;
+  uint64_t leaf_slot, leaf_pre, leaf_info, leaf_out, leaf_tgt, resid;
   uint64_t tiles, paths, hops;
   uint64_t static_end;  // [0, static_end) is uploaded with every deep copy
   uint64_t total;
@@ -207,12 +216,14 @@ struct Tables {  // device addresses of the scratch tables
   const uint64_t* leaf_pre;  // nleaves + 1 entries (16-byte chunk prefix)
   const uint64_t* leaf_info;
   const uint64_t* leaf_out;
+  const uint32_t* leaf_tgt;  // per leaf: global index of its parent slot's target entry
+  const DevResid* resid;     // the slots no leaf was first reached through
   const DevTile* tiles;
   const DevPath* paths;
   const uint64_t* hops;
   uint8_t* arena;
   uint64_t arena_bytes;
-  uint64_t nseg, nleaves, total_chunks;
+  uint64_t nseg, nleaves, total_chunks, nresid;
   uint32_t ntypes, pad;
 };
 
@@ -239,6 +250,12 @@ hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uin
 hipError_t launch_batch_units(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
                               hipStream_t s);
 hipError_t launch_reset_counters(DevHeader* hdr, hipStream_t s);
+// one launch that relocates and computes: every tile translates the parent
+// slots of the leaves whose first chunk it holds (attach before its compute,
+// detach after), extra workgroups translate the other slots; no workgroup
+// waits for another
+hipError_t launch_fused(const Tables& t, const LeafArgs& la, uint64_t ntiles, uint32_t tile_chunks, uint32_t flags,
+                        hipStream_t s);
 int device_cu_count();
 
 }  // namespace dc

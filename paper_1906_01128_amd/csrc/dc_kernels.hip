@@ -551,7 +551,8 @@ __device__ void leaf_tile(const Tables& t, const LeafArgs& la, uint64_t tile, ui
     }
   }
   if (tid == 0) pre[nl] = t.leaf_pre[l1 + 1];
-  __syncthreads();
+  // LDS only: nothing global written here is read by another thread
+  lds_barrier();
   for (uint64_t c_lo = tl.c_lo; c_lo < tl.c_hi; c_lo += (uint64_t)bs * U) {
     const uint64_t c_hi = tl.c_hi;
     if (!DEREF) {
@@ -620,13 +621,172 @@ __device__ void leaf_tile(const Tables& t, const LeafArgs& la, uint64_t tile, ui
       }
     }
   }
-  __syncthreads();
+  // the next tile's prologue rewrites the tables; no wait for this tile's stores
+  lds_barrier();
 }
 
 template <int U, bool DEREF>
 __global__ void __launch_bounds__(256) k_leaf_tiles(Tables t, LeafArgs la, uint64_t ntiles) {
   __shared__ __align__(16) uint8_t lds[kTileLds];
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) leaf_tile<U, DEREF>(t, la, tile, lds);
+}
+
+// ---- relocation and compute fused, tile by tile ------------------------------------------
+//
+// Every leaf is reached through one slot, its discovering slot, which only
+// the leaf's kernel reads. So a tile can translate the slots of its own
+// leaves: the tile holding a leaf's first chunk checks the slot and, after
+// its compute, writes the leaf's arena address into it (attach) and then the
+// host address back (detach), as the flags ask; another tile holding later
+// chunks of the same leaf accepts either value, since that first tile may run
+// before, during or after it. Each leaf is computed at its planned arena
+// address, the value the attach writes. Workgroups past the tiles translate every other slot (a
+// second reach of an array, a slot reaching a struct, integer or empty
+// array, null and unfollowed members). Nothing waits for anything: one launch
+// relocates and computes every structure.
+
+constexpr size_t kFusedLds = (size_t)(kTileMaxLeaves + 2) * 6 * 8;
+constexpr uint64_t kFirstBit = 1ull << 63;  // in the slot-offset table: this tile holds the leaf's first chunk
+
+template <int U>
+__device__ void fused_tile(const Tables& t, const LeafArgs& la, uint64_t tile, uint32_t flags, uint8_t* lds) {
+  constexpr uint32_t N = kTileMaxLeaves + 2;
+  uint64_t* pre = (uint64_t*)lds;
+  uint64_t* addr = pre + N;
+  uint64_t* info = addr + N;
+  uint64_t* outo = info + N;
+  uint64_t* soff = outo + N;
+  uint64_t* host = soff + N;
+  const bool att = (flags & DC_BATCH_ATTACH) != 0, det = (flags & DC_BATCH_DETACH) != 0;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const uint64_t B = (uint64_t)t.arena;
+  const DevTile tl = t.tiles[tile];
+  const uint32_t l0 = tl.l_lo, l1 = tl.l_hi;
+  const uint32_t nl = l1 - l0 + 1;
+  for (uint32_t i = tid; i < nl; i += bs) {
+    const uint32_t l = l0 + i;
+    const uint64_t pr = t.leaf_pre[l];
+    const uint64_t inf = t.leaf_info[l];
+    const uint64_t so = t.leaf_slot[l];
+    const uint32_t ti = t.leaf_tgt[l];
+    pre[i] = pr;
+    info[i] = inf;
+    outo[i] = t.leaf_out[l];
+    // the slot's value and the leaf's target entry in one round of loads
+    const bool sok = in_arena(t, B + so, 8);
+    const uint64_t v = sok ? *(const g_u64*)(B + so) : 0;
+    const DevTarget tg = t.tgts[ti];
+    const bool first = pr >= tl.c_lo;
+    const uint64_t dev = B + tg.off;
+    uint64_t a = 0;
+    if (sok && in_arena(t, dev, inf & ((1ull << kLeafKindShift) - 1))) {
+      // the value the slot holds before this launch touches it, and the one
+      // a first tile elsewhere may already have left in it
+      const uint64_t before = att ? tg.host : dev;
+      const uint64_t other = att ? dev : tg.host;
+      if (v == before || (!first && (att || det) && v == other)) a = dev;
+      else report_bad_slot(t.hdr, so);
+    } else {
+      report_wild(t.hdr);
+    }
+    addr[i] = a;
+    soff[i] = so | (first && a ? kFirstBit : 0);
+    host[i] = tg.host;
+  }
+  if (tid == 0) pre[nl] = t.leaf_pre[l1 + 1];
+  // LDS only: the attach stores need not complete before the compute
+  lds_barrier();
+  for (uint64_t c_lo = tl.c_lo; c_lo < tl.c_hi; c_lo += (uint64_t)bs * U) {
+    const uint64_t c_hi = tl.c_hi;
+    Vec16 v[U];
+    uint64_t src[U], dst[U];
+    uint32_t nb[U];
+    bool f64[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+      const uint64_t c = c_lo + (uint64_t)k * bs + tid;
+      nb[k] = 0;
+      f64[k] = false;
+      src[k] = dst[k] = 0;
+      if (c < c_hi) {
+        const uint32_t i = find_leaf(pre, nl, c);
+        const uint64_t byte = (c - pre[i]) * kChunk;
+        const uint64_t lb = info[i] & ((1ull << kLeafKindShift) - 1);
+        f64[k] = (info[i] >> kLeafKindShift) == DC_KIND_F64;
+        nb[k] = addr[i] == 0 ? 0 : (uint32_t)(lb - byte < kChunk ? lb - byte : kChunk);
+        src[k] = (la.src_out ? (uint64_t)la.out + outo[i] : addr[i]) + byte;
+        dst[k] = (la.out ? (uint64_t)la.out + outo[i] : addr[i]) + byte;
+      }
+      if (nb[k] == kChunk) v[k].u = gload16(src[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+      if (nb[k] == kChunk) {
+        fma_chunk_any(v[k], f64[k], la);
+        gstore16(dst[k], v[k].u);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; k++)
+      if (nb[k] != 0 && nb[k] != kChunk) fma_partial(src[k], dst[k], nb[k], f64[k] ? DC_KIND_F64 : DC_KIND_F32, la);
+  }
+  // the first tile of each leaf writes the slot: the arena address (attach),
+  // then the host address back (detach). Nothing in this launch needs the
+  // attached value (every tile computes at the planned address), so both
+  // stores come after the compute, by the thread that read the slot, in
+  // program order
+  if (att || det)
+    for (uint32_t i = tid; i < nl; i += bs)
+      if (soff[i] & kFirstBit) {
+        g_u64* slot = (g_u64*)(B + (soff[i] & ~kFirstBit));
+        if (att) *slot = addr[i];
+        if (det) *slot = host[i];
+      }
+  lds_barrier();
+}
+
+// bs of the other slots: translated as the relocation kernel would (attach,
+// then detach when both are asked for)
+__device__ void fused_resid(const Tables& t, uint64_t blk, uint32_t flags) {
+  const uint64_t k = blk * blockDim.x + threadIdx.x;
+  if (k >= t.nresid) return;
+  const bool att = (flags & DC_BATCH_ATTACH) != 0, det = (flags & DC_BATCH_DETACH) != 0;
+  const uint64_t B = (uint64_t)t.arena;
+  const DevResid r = t.resid[k];
+  if (!in_arena(t, B + r.slot_off, 8)) {
+    report_wild(t.hdr);
+    return;
+  }
+  g_u64* slot = (g_u64*)(B + r.slot_off);
+  const uint64_t v = *slot;
+  if (v == 0) return;
+  // a member left out of a selective copy reads as null on the device
+  if (!r.follow) {
+    *slot = 0;
+    return;
+  }
+  if (r.tgt == kNone) {
+    report_bad_slot(t.hdr, r.slot_off);
+    return;
+  }
+  const DevTarget tg = t.tgts[r.tgt];
+  const uint64_t dev = B + tg.off;
+  if (v != (att ? tg.host : dev)) {
+    report_bad_slot(t.hdr, r.slot_off);
+    return;
+  }
+  if (att) *slot = dev;
+  if (det) *slot = tg.host;
+}
+
+template <int U>
+__global__ void __launch_bounds__(256) k_fused(Tables t, LeafArgs la, uint64_t ntiles, uint64_t nitems,
+                                               uint32_t flags) {
+  __shared__ __align__(16) uint8_t lds[kFusedLds];
+  for (uint64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+    if (item < ntiles) fused_tile<U>(t, la, item, flags, lds);
+    else fused_resid(t, item - ntiles, flags);
+  }
 }
 
 // ---- molecular dynamics: kick then drift on sibling leaves ------------------------------
@@ -668,7 +828,7 @@ __global__ void __launch_bounds__(256) k_kick_drift(Tables t, KickDriftArgs k) {
       cnt[i] = tr.count;
     }
     if (tid == 0) pre[nl] = k.pre[tl.l_hi + 1];
-    __syncthreads();
+    lds_barrier();  // the element table; no global memory is shared between threads
     for (uint64_t c_lo = tl.c_lo; c_lo < tl.c_hi; c_lo += (uint64_t)bs * U) {
       Vec16 X[U], V[U], F[U];
       uint64_t xd[U], vd[U];
@@ -711,7 +871,7 @@ __global__ void __launch_bounds__(256) k_kick_drift(Tables t, KickDriftArgs k) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier();  // before the next tile rewrites the table; no wait for this tile's stores
   }
 }
 
@@ -1115,6 +1275,18 @@ hipError_t launch_batch_units(const Tables& t, const LeafArgs& la, uint32_t flag
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(const Tables& t, const LeafArgs& la, uint64_t ntiles, uint32_t tile_chunks, uint32_t flags,
+                        hipStream_t s) {
+  const uint64_t nitems = ntiles + (t.nresid + 255) / 256;
+  if (nitems == 0) return hipSuccess;
+  const uint64_t grid = nitems < (1u << 20) ? nitems : (1u << 20);
+  if (tile_chunks <= 512)
+    hipLaunchKernelGGL((k_fused<2>), dim3((uint32_t)grid), dim3(256), 0, s, t, la, ntiles, nitems, flags);
+  else
+    hipLaunchKernelGGL((k_fused<4>), dim3((uint32_t)grid), dim3(256), 0, s, t, la, ntiles, nitems, flags);
   return hipGetLastError();
 }
 

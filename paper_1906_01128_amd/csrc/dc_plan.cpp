@@ -705,6 +705,50 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     if (p->unit_leaves)
       for (uint64_t c = 0; c < nch; c++) p->max_unit_leaf_chunks = std::max(p->max_unit_leaf_chunks, cmax[c]);
   }
+  // the fused relocate-and-compute launch: each leaf's parent slot's target
+  // entry, and every other slot with its arena offset (slots, units and
+  // leaves of a chunk stay within the chunk)
+  {
+    p->leaf_tgt.resize(p->leaves.size());
+    std::vector<std::vector<DevResid>> cres(nch);
+    each_chunk([&](int c) {
+      const uint64_t s0 = sbase[c], s1 = sbase[c + 1];
+      auto unit_of = [&](uint64_t slot) {  // last unit of the chunk starting at or before slot
+        uint64_t lo = s0, hi = s1;
+        while (hi - lo > 1) {
+          const uint64_t mid = (lo + hi) / 2;
+          if (p->segs[mid].slot_lo <= slot) lo = mid;
+          else hi = mid;
+        }
+        return lo;
+      };
+      for (uint64_t l = lbase[c]; l < lbase[c + 1]; l++) {
+        const uint64_t slot = p->objs[p->leaves[l]].slot;
+        p->leaf_tgt[l] = (uint32_t)(p->segs[unit_of(slot)].tgt_lo + p->slot_tix[slot]);
+      }
+      uint64_t u = s0;
+      for (uint64_t so = csobj[c]; so < csobj[c + 1]; so++) {
+        const DevSObj& sob = p->sobj[so];
+        const TypeDesc& ty = p->types[sob.type];
+        const uint64_t nptr = ty.order.size();
+        for (uint64_t j = p->sobj_pre[so]; j < p->sobj_pre[so + 1]; j++) {
+          while (u + 1 < s1 && p->segs[u + 1].slot_lo <= j) u++;
+          const uint32_t t = p->slot_target[j];
+          if (t != kNone) {
+            const Obj& o = p->objs[t];
+            if ((o.kind == DC_KIND_F32 || o.kind == DC_KIND_F64) && o.count && o.slot == j) continue;  // a leaf's
+          }
+          const uint64_t local = j - p->sobj_pre[so], e = local / nptr, f = local % nptr;
+          DevResid r;
+          r.slot_off = sob.off + e * ty.size + ty.fields[ty.order[f]].offset;
+          r.tgt = t == kNone ? kNone : (uint32_t)(p->segs[u].tgt_lo + p->slot_tix[j]);
+          r.follow = (ty.follow >> ty.order[f]) & 1u;
+          cres[c].push_back(r);
+        }
+      }
+    });
+    for (uint64_t c = 0; c < nch; c++) p->resid.insert(p->resid.end(), cres[c].begin(), cres[c].end());
+  }
   lk = std::unique_lock<std::mutex>();  // the pool is free for other plans
 
   // device types
@@ -749,6 +793,8 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     s.leaf_pre = take(8 * (nl + 1));
     s.leaf_info = take(8 * nl);
     s.leaf_out = take(8 * nl);
+    s.leaf_tgt = take(4 * nl);
+    s.resid = take(sizeof(DevResid) * p->resid.size());
     s.static_end = at;
     const uint64_t max_tiles = (p->total_chunks + kTileMinChunks - 1) / kTileMinChunks +
                                p->leaves.size() / (kTileMaxLeaves - 1) + 2;

@@ -31,6 +31,18 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Whether [p, p + n) lies in page-locked host memory, which the copy engine
+// can write directly. A failed query (pageable memory) leaves an error that
+// a later hipGetLastError of this thread would report: it is cleared.
+static bool pinned_host(const void* p, uint64_t n) {
+  if (!p || !n) return false;
+  hipPointerAttribute_t a, b;
+  const bool ok = hipPointerGetAttributes(&a, p) == hipSuccess && a.type == hipMemoryTypeHost &&
+                  hipPointerGetAttributes(&b, (const uint8_t*)p + n - 1) == hipSuccess && b.type == hipMemoryTypeHost;
+  if (!ok) (void)hipGetLastError();
+  return ok;
+}
+
 // First-fit allocator over one device allocation of the budget's size.
 class DevicePool {
  public:
@@ -389,24 +401,36 @@ void dc_server_s::done_loop() {
     uint8_t* out = (uint8_t*)j->req.out_host;
     const dc_plan_s* p = j->res->plan;
     // only the leaves' bytes go to the caller: bytes between leaves in the
-    // image are never written, as for an out-of-place dc_run_kernel
-    st = download(done_ctx, j->d_out, 0, j->out_bytes, s, [&](const uint8_t* buf, uint64_t lo, uint64_t hi) {
-      // split the chunk among the pool's threads; each copies the leaf
-      // bytes that fall in its part
-      const uint64_t part = 1ull << 20;
-      const int nparts = (int)((hi - lo + part - 1) / part);
-      done_ctx->pool->run(nparts, [&](int k) {
-        const uint64_t plo = lo + (uint64_t)k * part, phi = std::min(hi, plo + part);
-        size_t l = std::upper_bound(p->leaf_out.begin(), p->leaf_out.end(), plo) - p->leaf_out.begin();
-        if (l > 0) l--;
-        for (; l < p->leaf_out.size() && p->leaf_out[l] < phi; l++) {
-          const uint64_t a = std::max(plo, p->leaf_out[l]);
-          const uint64_t b =
-              std::min<uint64_t>(phi, p->leaf_out[l] + (p->leaf_info[l] & ((1ull << kLeafKindShift) - 1)));
-          if (b > a) copy_stream(out + a, buf + (a - lo), b - a);
-        }
+    // image are never written, as for an out-of-place dc_run_kernel. Into a
+    // page-locked buffer each leaf goes by its own copy, straight from the
+    // device (one pass over host memory instead of three: copy into the
+    // staging ring, read it, write the buffer)
+    if (pinned_host(out, j->out_bytes)) {
+      for (size_t l = 0; l < p->leaves.size() && st == DC_OK; l++) {
+        const uint64_t a = p->leaf_out[l], n = p->leaf_info[l] & ((1ull << kLeafKindShift) - 1);
+        if (n && hipMemcpyAsync(out + a, j->d_out + a, n, hipMemcpyDeviceToHost, s) != hipSuccess)
+          st = fail(DC_E_HIP, "leaf copy back");
+      }
+      if (st == DC_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(DC_E_HIP, "leaf copy back");
+    } else {
+      st = download(done_ctx, j->d_out, 0, j->out_bytes, s, [&](const uint8_t* buf, uint64_t lo, uint64_t hi) {
+        // split the chunk among the pool's threads; each copies the leaf
+        // bytes that fall in its part
+        const uint64_t part = 1ull << 20;
+        const int nparts = (int)((hi - lo + part - 1) / part);
+        done_ctx->pool->run(nparts, [&](int k) {
+          const uint64_t plo = lo + (uint64_t)k * part, phi = std::min(hi, plo + part);
+          size_t l = std::upper_bound(p->leaf_out.begin(), p->leaf_out.end(), plo) - p->leaf_out.begin();
+          if (l > 0) l--;
+          for (; l < p->leaf_out.size() && p->leaf_out[l] < phi; l++) {
+            const uint64_t a = std::max(plo, p->leaf_out[l]);
+            const uint64_t b =
+                std::min<uint64_t>(phi, p->leaf_out[l] + (p->leaf_info[l] & ((1ull << kLeafKindShift) - 1)));
+            if (b > a) copy_stream(out + a, buf + (a - lo), b - a);
+          }
+        });
       });
-    });
+    }
     if (st == DC_OK) st = tree_check(j->res->tree, s);
     if (st != DC_OK) err = dc_last_error();
     lk.lock();

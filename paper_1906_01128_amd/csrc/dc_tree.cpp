@@ -22,6 +22,9 @@ static Tables make_tables(dc_plan p, uint8_t* arena, uint8_t* scratch) {
   t.leaf_pre = (const uint64_t*)(scratch + s.leaf_pre);
   t.leaf_info = (const uint64_t*)(scratch + s.leaf_info);
   t.leaf_out = (const uint64_t*)(scratch + s.leaf_out);
+  t.leaf_tgt = (const uint32_t*)(scratch + s.leaf_tgt);
+  t.resid = (const DevResid*)(scratch + s.resid);
+  t.nresid = p->resid.size();
   t.tiles = (const DevTile*)(scratch + s.tiles);
   t.paths = (const DevPath*)(scratch + s.paths);
   t.hops = (const uint64_t*)(scratch + s.hops);
@@ -77,6 +80,8 @@ static dc_status upload_tables(dc_ctx ctx, dc_plan p, uint8_t* arena, uint8_t* s
   add(sl.leaf_pre, p->leaf_pre.data(), 8 * p->leaf_pre.size());
   add(sl.leaf_info, p->leaf_info.data(), 8 * p->leaf_info.size());
   add(sl.leaf_out, p->leaf_out.data(), 8 * p->leaf_out.size());
+  add(sl.leaf_tgt, p->leaf_tgt.data(), 4 * p->leaf_tgt.size());
+  add(sl.resid, p->resid.data(), sizeof(DevResid) * p->resid.size());
   // packing is synchronous, so the header copy may live on the stack
   return upload_pieces(ctx, scratch, sl.static_end, pcs, s);
 }

@@ -198,6 +198,12 @@ hipError_t hipEventSynchronize(hipEvent_t e) {
   st->cv.wait(lk, [&] { return st->done >= st->recorded; });
   return hipSuccess;
 }
+// no host memory is page-locked here: buffers are treated as pageable
+hipError_t hipPointerGetAttributes(hipPointerAttribute_t* a, const void*) {
+  memset(a, 0, sizeof(*a));
+  return hipErrorInvalidValue;
+}
+hipError_t hipGetLastError() { return hipSuccess; }
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) {
   *ms = 0.001f;
   return hipSuccess;
@@ -264,4 +270,5 @@ hipError_t launch_batch_units(const Tables&, const LeafArgs&, uint32_t, uint32_t
   return launch(s);
 }
 hipError_t launch_reset_counters(DevHeader*, hipStream_t s) { return launch(s); }
+hipError_t launch_fused(const Tables&, const LeafArgs&, uint64_t, uint32_t, uint32_t, hipStream_t s) { return launch(s); }
 }  // namespace dc

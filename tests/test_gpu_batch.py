@@ -50,7 +50,9 @@ SHAPES = [None,
           dict(block=1024, wg_per_cu=1, tile_chunks=65536, launches=2),
           dict(block=256, wg_per_cu=4, tile_chunks=1 << 20, launches=2),
           # three launches
-          dict(tile_chunks=1024, launches=1), dict(tile_chunks=4096, launches=1)]
+          dict(tile_chunks=1024, launches=1), dict(tile_chunks=4096, launches=1),
+          # one fused launch: tiles relocate their own leaves' slots
+          dict(tile_chunks=512, launches=3), dict(tile_chunks=1024, launches=3), dict(tile_chunks=65536, launches=3)]
 
 
 @pytest.mark.parametrize("tune", SHAPES)
@@ -64,7 +66,7 @@ def test_batch_attach_detach_any_tile_shape(ctx, tune):
     c.tree.check()
 
 
-@pytest.mark.parametrize("launches", [0, 1, 2])
+@pytest.mark.parametrize("launches", [0, 1, 2, 3])
 def test_batch_each_flag_combination(ctx, launches):
     """ATTACH alone, then neither (compute on the attached tree), then DETACH
     alone, each compared with the oracle's arena at that point: attached and
@@ -84,7 +86,7 @@ def test_batch_each_flag_combination(ctx, launches):
     c.tree.check()
 
 
-@pytest.mark.parametrize("launches", [0, 2])
+@pytest.mark.parametrize("launches", [0, 2, 3])
 def test_batch_units_not_contiguous(ctx, launches):
     """A 16-way Dense tree: its relocation units do not own contiguous leaf
     runs, so the persistent launch runs in three phases either way."""
@@ -129,7 +131,7 @@ def test_batch_wide_and_out_of_place(ctx):
     assert_same_bytes(c.device_arena(), c.oracle.arena(), "arena relocated, leaves untouched")
 
 
-@pytest.mark.parametrize("launches", [0, 1])
+@pytest.mark.parametrize("launches", [0, 1, 3])
 def test_graph_replays(ctx, launches):
     t = fx.md(seed=6, nsims=40, cells_lo=2, cells_hi=30, mean_atoms=8)
     c = Copy(ctx, t, relocate=False)
@@ -181,10 +183,11 @@ def test_autotune_then_parity(ctx, tmp_path, monkeypatch):
     t = fx.md(seed=8, nsims=200, cells_lo=4, cells_hi=64, mean_atoms=16)
     c = Copy(ctx, t, relocate=False)
     choice = c.tree.autotune(reps=1)
-    assert choice["block"] in (256, 512, 1024) and choice["launches"] in (0, 1, 2)
+    assert choice["block"] in (256, 512, 1024) and choice["launches"] in (0, 1, 2, 3)
     table = c.tree.autotune_results()
     assert len(table) >= 8 and choice in [tu for tu, _ in table]
-    assert all(tu["block"] * tu["wg_per_cu"] <= 2048 for tu, _ in table if tu["launches"] != 1)
+    assert all(tu["block"] * tu["wg_per_cu"] <= 2048 for tu, _ in table if tu["launches"] in (0, 2))
+    assert any(tu["launches"] == 3 for tu, _ in table)
     assert any(tu["block"] == 1024 for tu, _ in table)
     assert (tmp_path / "tune.json").exists()
     # the autotuner changed leaf values; copy again and run with the cached choice
@@ -217,7 +220,8 @@ def md_full(ctx):
 @pytest.mark.slow
 @pytest.mark.parametrize("tune", [dict(block=1024, wg_per_cu=2, launches=0),
                                   dict(block=1024, wg_per_cu=2, tile_chunks=16384, launches=2),
-                                  dict(tile_chunks=1024, launches=1)])
+                                  dict(tile_chunks=1024, launches=1),
+                                  dict(tile_chunks=1024, launches=3)])
 def test_batch_md_full_size(ctx, md_full, tune):
     """10,000 simulations, ~7.8 M arrays, ~12 GB, in each batched form with
     an explicit shape (the per-unit persistent launch, the three-phase
@@ -303,3 +307,38 @@ def test_autotune_and_graph_right_after_staging(ctx, tmp_path, monkeypatch):
     g.close()
     tree.release()
     ref.free()
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("detach", [False, True])
+def test_fused_random_graphs(ctx, seed, detach):
+    """The fused launch on random pointer graphs: null members, arrays reached
+    twice (the second slot is translated apart from the tiles), cycles,
+    zero-length arrays and struct arrays, several roots; 512-chunk tiles so
+    that long leaves span several tiles."""
+    t = fx.random_tree(5100 + seed, max_objects=80, nroots=1 + seed % 3)
+    c = Copy(ctx, t, align=[16, 64, 256][seed % 3], relocate=False)
+    ref = c.oracle
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=detach, tune=dict(tile_chunks=512, launches=3))
+    ref.run_kernel(1.0001, 0.5, iters=1, select="all")
+    if detach:
+        assert_same_bytes(c.device_arena(), _staged_after_kernel(c, 1), f"fused attach+detach seed {seed}")
+    else:
+        assert_same_bytes(c.device_arena(), ref.arena(), f"fused attach seed {seed}")
+        # and detach alone afterwards, with one more pass
+        c.tree.batch_run(a=1.0001, b=0.5, attach=False, detach=True, tune=dict(tile_chunks=512, launches=3))
+        assert_same_bytes(c.device_arena(), _staged_after_kernel(c, 2), f"fused detach seed {seed}")
+    c.tree.check()
+
+
+def test_fused_selective_and_long_leaves(ctx):
+    """A selective copy (unfollowed members are zeroed, apart from the
+    tiles) and leaves of up to 40,000 elements spread over many 512-chunk
+    tiles, compared with the oracle after attach, and after attach + detach."""
+    t = fx.wide(seed=91, f1=6, f2=9, lo=1, hi=40000)
+    follow = [0b1, 0b1, 0b01]   # the leaf structs follow their f32 member only
+    c = Copy(ctx, t, relocate=False, follow=follow)
+    c.tree.batch_run(a=0.9999, b=-0.25, attach=True, detach=False, tune=dict(tile_chunks=512, launches=3))
+    c.oracle.run_kernel(0.9999, -0.25, iters=1, select="all")
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), "fused selective attach")
+    c.tree.check()

@@ -186,3 +186,30 @@ def test_failed_admission_is_not_kept(ctx):
     for k in (0, 2, 3):
         si, _, ab = jobs[k]
         assert np.array_equal(outs[k], _expected(structs[si], *AB[ab])), f"job {k}"
+
+
+def test_pinned_outputs_equal_pageable_and_oracle(ctx):
+    """Jobs whose output buffers are page-locked receive every leaf by a direct
+    copy; the whole image (the bytes between leaves left as the caller set
+    them) equals the oracle's and the pageable path's."""
+    from paper_1906_01128_amd import dc
+    structs = _structures(6, 8 << 20, seed=400)
+    schema = dc.Schema(structs[0].types)
+    jobs = [(i % 6, (i % 6) + 1 if i % 2 else 0, i % 4) for i in range(12)]
+    srv = dc.Server(ctx, schema, budget_bytes=2 << 30, max_inflight=4, nstreams=2)
+    pinned, ids = [], []
+    for si, key, ab in jobs:
+        t = structs[si]
+        n = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 0).out_bytes("all")
+        buf = torch.full((max(n, 1),), 0, dtype=torch.uint8, pin_memory=True)
+        pinned.append(buf)
+        ids.append(srv.submit(t.root_type, t.roots[0], buf.data_ptr(), buf.numel(), *AB[ab], key=key))
+    res = [srv.wait(i, timeout=120.0) for i in ids]
+    assert all(r.status == 0 for r in res)
+    pageable, _ = _run(srv, jobs, structs)
+    srv.close()
+    for k, (si, _, ab) in enumerate(jobs):
+        want = _expected(structs[si], *AB[ab])
+        got = pinned[k].numpy()
+        assert np.array_equal(got[: want.nbytes], want), f"job {k}: pinned output differs from the oracle"
+        assert np.array_equal(pageable[k][: want.nbytes], want), f"job {k}: pageable output differs from the oracle"
