@@ -64,3 +64,37 @@ def test_all_leaves_skip_a_wild_leaf(ctx, mode):
     with pytest.raises(dc.DcError):
         c.tree.check()
     assert torch.equal(c.arena[leaf_off: leaf_off + 8 * N], before)
+
+
+@pytest.mark.parametrize("launches", [0, 1, 2, 3])
+def test_batched_forms_skip_a_wild_slot(ctx, launches):
+    """In every batched form (per-unit persistent, three launches, three-phase
+    persistent, fused), a leaf whose member was overwritten with an address
+    outside the arena is neither attached nor computed, the error is
+    reported, and nothing past the arena is written."""
+    from paper_1906_01128_amd import dc
+    t = fx.md(seed=fx.SEED_BASE + 62, nsims=20, cells_lo=2, cells_hi=6, mean_atoms=8)
+    schema = dc.Schema(t.types)
+    plan = dc.Plan(schema, t.root_type, t.roots)
+    guard = 1 << 16
+    arena = torch.zeros(plan.arena_bytes + guard, dtype=torch.uint8, device="cuda")
+    scratch = torch.empty(plan.scratch_bytes, dtype=torch.uint8, device="cuda")
+    tree = dc.Tree(ctx, plan, arena, scratch, relocate=False)
+    torch.cuda.synchronize()
+    objs = plan.objects()
+    cells = [o for o in objs if o["kind"] == 0 and o["type"] == 1][3]
+    slot = int(cells["off"]) + 32 + 8                      # cell 1's position member
+    host = int.from_bytes(bytes(arena[slot: slot + 8].cpu().numpy()), "little")
+    leaf = [o for o in objs if int(o["host"]) == host][0]
+    lo, hi = int(leaf["off"]), int(leaf["off"]) + int(leaf["bytes"])
+    arena[slot: slot + 8] = torch.tensor(np.frombuffer((0xFFFF000000000000).to_bytes(8, "little"), np.uint8).copy(),
+                                         device="cuda")
+    before = arena[lo:hi].clone()
+    print(f"[gpu] wild slot at {slot}, batched form {launches}", flush=True)
+    tree.batch_run(a=2.0, b=1.0, attach=True, detach=True, tune=dict(tile_chunks=1024, launches=launches))
+    torch.cuda.synchronize()
+    with pytest.raises(dc.DcError):
+        tree.check()
+    assert torch.equal(arena[lo:hi], before), "the leaf behind the wild member was computed"
+    assert int(arena[plan.arena_bytes:].count_nonzero()) == 0, "bytes past the arena were written"
+    tree.release()
