@@ -217,6 +217,7 @@ struct dc_plan_s {
   // leaves (FP32/FP64 arrays with >= 1 element), arena order
   dc::bigvec<uint32_t> leaves;
   dc::bigvec<uint64_t> leaf_pre, leaf_info, leaf_slot, leaf_out;
+  dc::bigvec<uint64_t> leaf_dev;       // per leaf: its planned arena offset
   dc::bigvec<uint32_t> leaf_tgt;       // per leaf: global index of its parent slot's target entry
   std::vector<dc::DevResid> resid;     // slots that are no leaf's discovering slot
   uint64_t out_bytes = 0, total_chunks = 0, total_hops = 0;

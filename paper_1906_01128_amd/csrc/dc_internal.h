@@ -132,7 +132,7 @@ enum DevErr : uint32_t {
 
 struct ScratchLayout {
   uint64_t header, types, sobj, sobj_pre, segs, tgts, slot_tix;
-  uint64_t leaf_slot, leaf_pre, leaf_info, leaf_out, leaf_tgt, resid;
+  uint64_t leaf_slot, leaf_pre, leaf_info, leaf_out, leaf_tgt, leaf_dev, resid;
   uint64_t tiles, paths, hops;
   uint64_t static_end;  // [0, static_end) is uploaded with every deep copy
   uint64_t total;
@@ -217,6 +217,7 @@ struct Tables {  // device addresses of the scratch tables
   const uint64_t* leaf_info;
   const uint64_t* leaf_out;
   const uint32_t* leaf_tgt;  // per leaf: global index of its parent slot's target entry
+  const uint64_t* leaf_dev;  // per leaf: its planned arena offset
   const DevResid* resid;     // the slots no leaf was first reached through
   const DevTile* tiles;
   const DevPath* paths;

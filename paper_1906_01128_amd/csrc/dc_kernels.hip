@@ -515,113 +515,178 @@ __device__ __forceinline__ uint32_t find_leaf(const uint64_t* pre, uint32_t nl, 
   return lo;
 }
 
-// LDS of one compute tile: prefix, address, size|kind and image offset of up
-// to kTileMaxLeaves leaves (and one more prefix entry)
-constexpr size_t kTileLds = (size_t)(kTileMaxLeaves + 2) * 4 * 8;
+// LDS of one compute tile: prefix, address, size|kind, image offset and
+// followed address of up to kTileMaxLeaves leaves (and one more prefix entry)
+constexpr size_t kTileLds = (size_t)(kTileMaxLeaves + 2) * 5 * 8;
+// a RESOLVED tile gives each of its leaves a thread of its own (launches have 256, 512 or 1024)
+static_assert(kTileMaxLeaves <= 256, "one leaf per thread in the tile prologue");
+
+// One round of a RESOLVED tile: chunk c_lo + k * bs + tid for k < U, each
+// read from its leaf at base[i] (or from the image) when whole.
+struct TileRound {
+  Vec16 v;
+  uint64_t byte;
+  uint32_t i, nb;
+};
+
+template <int U>
+__device__ __forceinline__ void tile_round_load(const LeafArgs& la, const uint64_t* pre, const uint64_t* base,
+                                                const uint64_t* info, const uint64_t* outo, uint32_t nl,
+                                                uint64_t c_lo, uint64_t c_hi, TileRound (&r)[U]) {
+  const int tid = threadIdx.x, bs = blockDim.x;
+#pragma unroll
+  for (int k = 0; k < U; k++) {
+    const uint64_t c = c_lo + (uint64_t)k * bs + tid;
+    r[k].nb = 0;
+    r[k].i = 0;
+    r[k].byte = 0;
+    if (c < c_hi) {
+      const uint32_t i = find_leaf(pre, nl, c);
+      const uint64_t byte = (c - pre[i]) * kChunk;
+      const uint64_t lb = info[i] & ((1ull << kLeafKindShift) - 1);
+      r[k].i = i;
+      r[k].byte = byte;
+      r[k].nb = base[i] == 0 ? 0 : (uint32_t)(lb - byte < kChunk ? lb - byte : kChunk);
+      const uint64_t src = (la.src_out ? (uint64_t)la.out + outo[i] : base[i]) + byte;
+      if (r[k].nb == kChunk) r[k].v.u = gload16(src);
+    }
+  }
+}
+
+template <int U>
+__device__ __forceinline__ void tile_round_store(const LeafArgs& la, const uint64_t* addr, const uint64_t* info,
+                                                 const uint64_t* outo, TileRound (&r)[U]) {
+#pragma unroll
+  for (int k = 0; k < U; k++) {
+    if (r[k].nb == kChunk) {
+      const uint32_t i = r[k].i;
+      fma_chunk_any(r[k].v, (info[i] >> kLeafKindShift) == DC_KIND_F64, la);
+      gstore16((la.out ? (uint64_t)la.out + outo[i] : addr[i]) + r[k].byte, r[k].v.u);
+    }
+  }
+  // the last, shorter chunk of a leaf, element by element
+#pragma unroll
+  for (int k = 0; k < U; k++) {
+    if (r[k].nb != 0 && r[k].nb != kChunk) {
+      const uint32_t i = r[k].i;
+      const uint64_t src = (la.src_out ? (uint64_t)la.out + outo[i] : addr[i]) + r[k].byte;
+      const uint64_t dst = (la.out ? (uint64_t)la.out + outo[i] : addr[i]) + r[k].byte;
+      fma_partial(src, dst, r[k].nb, (uint32_t)(info[i] >> kLeafKindShift), la);
+    }
+  }
+}
 
 // One compute tile: its chunk range of the leaves laid end to end, processed
 // in rounds of U chunks per thread. RESOLVED: each leaf's address is read
-// once per tile from its relocated parent slot. DEREF: each element access
-// walks the leaf's whole path from its root.
+// once per tile from its relocated parent slot; the first round's loads are
+// issued at the leaf's planned address together with that slot read, and a
+// chunk whose slot turns out to hold another address is read again from
+// there before anything is stored, so the result is that of following the
+// slot. DEREF: each element access walks the leaf's whole path from its root.
 template <int U, bool DEREF>
 __device__ void leaf_tile(const Tables& t, const LeafArgs& la, uint64_t tile, uint8_t* lds) {
   constexpr uint32_t N = kTileMaxLeaves + 2;
   uint64_t* pre = (uint64_t*)lds;
-  uint64_t* addr = pre + N;
+  uint64_t* addr = pre + N;   // RESOLVED: the followed address (0: wild); first the planned one
   uint64_t* info = addr + N;
   uint64_t* outo = info + N;
+  uint64_t* plan = outo + N;  // RESOLVED: the planned address (0: outside the arena)
   const int tid = threadIdx.x, bs = blockDim.x;
+  const uint64_t B = (uint64_t)t.arena;
   const DevTile tl = t.tiles[tile];
   const uint32_t l0 = tl.l_lo, l1 = tl.l_hi;
   const uint32_t nl = l1 - l0 + 1;
+  if (!DEREF) {
+    // one leaf per thread: every launch has at least kTileMaxLeaves threads
+    uint64_t so = 0, lb = 0;
+    if (tid < (int)nl) {
+      const uint32_t l = l0 + tid;
+      pre[tid] = t.leaf_pre[l];
+      const uint64_t inf = t.leaf_info[l];
+      info[tid] = inf;
+      outo[tid] = t.leaf_out[l];
+      so = t.leaf_slot[l];
+      lb = inf & ((1ull << kLeafKindShift) - 1);
+      const uint64_t pl = B + t.leaf_dev[l];
+      plan[tid] = in_arena(t, pl, lb) ? pl : 0;
+    }
+    if (tid == 0) pre[nl] = t.leaf_pre[l1 + 1];
+    lds_barrier();
+    TileRound r[U];
+    tile_round_load<U>(la, pre, plan, info, outo, nl, tl.c_lo, tl.c_hi, r);
+    // the parent slots, read while those loads are in flight
+    if (tid < (int)nl) {
+      const uint64_t a = *(const g_u64*)(B + so);
+      if (in_arena(t, a, lb)) {
+        addr[tid] = a;
+      } else {
+        addr[tid] = 0;
+        report_wild(t.hdr);
+      }
+    }
+    lds_barrier();
+    // a chunk loaded from anywhere but its slot's address is loaded again
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+      const uint64_t c = tl.c_lo + (uint64_t)k * bs + tid;
+      if (c < tl.c_hi && addr[r[k].i] != plan[r[k].i]) {
+        const uint32_t i = r[k].i;
+        const uint64_t lb2 = info[i] & ((1ull << kLeafKindShift) - 1);
+        r[k].nb = addr[i] == 0 ? 0 : (uint32_t)(lb2 - r[k].byte < kChunk ? lb2 - r[k].byte : kChunk);
+        const uint64_t src = (la.src_out ? (uint64_t)la.out + outo[i] : addr[i]) + r[k].byte;
+        if (r[k].nb == kChunk) r[k].v.u = gload16(src);
+      }
+    }
+    tile_round_store<U>(la, addr, info, outo, r);
+    for (uint64_t c_lo = tl.c_lo + (uint64_t)bs * U; c_lo < tl.c_hi; c_lo += (uint64_t)bs * U) {
+      tile_round_load<U>(la, pre, addr, info, outo, nl, c_lo, tl.c_hi, r);
+      tile_round_store<U>(la, addr, info, outo, r);
+    }
+    // the next tile's prologue rewrites the tables; no wait for this tile's stores
+    lds_barrier();
+    return;
+  }
   for (uint32_t i = tid; i < nl; i += bs) {
     const uint32_t l = l0 + i;
     pre[i] = t.leaf_pre[l];
     info[i] = t.leaf_info[l];
     outo[i] = t.leaf_out[l];
-    if (!DEREF) {
-      const uint64_t a = *(const g_u64*)((uint64_t)t.arena + t.leaf_slot[l]);
-      const uint64_t lb = t.leaf_info[l] & ((1ull << kLeafKindShift) - 1);
-      if (in_arena(t, a, lb)) {
-        addr[i] = a;
-      } else {
-        addr[i] = 0;
-        report_wild(t.hdr);
-      }
-    }
   }
   if (tid == 0) pre[nl] = t.leaf_pre[l1 + 1];
   // LDS only: nothing global written here is read by another thread
   lds_barrier();
   for (uint64_t c_lo = tl.c_lo; c_lo < tl.c_hi; c_lo += (uint64_t)bs * U) {
     const uint64_t c_hi = tl.c_hi;
-    if (!DEREF) {
-      Vec16 v[U];
-      uint64_t src[U], dst[U];
-      uint32_t nb[U];
-      bool f64[U];
-#pragma unroll
-      for (int k = 0; k < U; k++) {
-        const uint64_t c = c_lo + (uint64_t)k * bs + tid;
-        nb[k] = 0;
-        f64[k] = false;
-        src[k] = dst[k] = 0;
-        if (c < c_hi) {
-          const uint32_t i = find_leaf(pre, nl, c);
-          const uint64_t byte = (c - pre[i]) * kChunk;
-          const uint64_t lb = info[i] & ((1ull << kLeafKindShift) - 1);
-          f64[k] = (info[i] >> kLeafKindShift) == DC_KIND_F64;
-          nb[k] = addr[i] == 0 ? 0 : (uint32_t)(lb - byte < kChunk ? lb - byte : kChunk);
-          src[k] = (la.src_out ? (uint64_t)la.out + outo[i] : addr[i]) + byte;
-          dst[k] = (la.out ? (uint64_t)la.out + outo[i] : addr[i]) + byte;
-        }
-        if (nb[k] == kChunk) v[k].u = gload16(src[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < U; k++) {
-        if (nb[k] == kChunk) {
-          fma_chunk_any(v[k], f64[k], la);
-          gstore16(dst[k], v[k].u);
-        }
-      }
-      // the last, shorter chunk of a leaf, element by element
-#pragma unroll
-      for (int k = 0; k < U; k++)
-        if (nb[k] != 0 && nb[k] != kChunk)
-          fma_partial(src[k], dst[k], nb[k], f64[k] ? DC_KIND_F64 : DC_KIND_F32, la);
-    } else {
 #pragma unroll 1
-      for (int k = 0; k < U; k++) {
-        const uint64_t c = c_lo + (uint64_t)k * bs + tid;
-        if (c >= c_hi) continue;
-        const uint32_t i = find_leaf(pre, nl, c);
-        const uint64_t byte = (c - pre[i]) * kChunk;
-        const uint64_t lb = info[i] & ((1ull << kLeafKindShift) - 1);
-        const uint32_t kind = (uint32_t)(info[i] >> kLeafKindShift);
-        const uint32_t n = (uint32_t)(lb - byte < kChunk ? lb - byte : kChunk);
-        const DevPath path = t.paths[l0 + i];
-        const uint32_t es = kind == DC_KIND_F64 ? 8 : 4;
-        for (uint32_t o = 0; o + es <= n; o += es) {
-          const uint8_t* p = t.arena + path.root_off;
-          bool ok = true;
-          for (uint32_t hp = 0; hp < path.nhops && ok; hp++) {
-            const uint8_t* slot = opaque(p) + t.hops[path.hop_lo + hp];
-            ok = in_arena(t, (uint64_t)slot, 8);
-            if (ok) p = (const uint8_t*)*(const g_u64*)(uint64_t)slot;
-          }
-          if (!ok || !in_arena(t, (uint64_t)p, lb)) {
-            report_wild(t.hdr);
-            break;
-          }
-          const uint64_t src = (la.src_out ? (uint64_t)la.out + outo[i] : (uint64_t)p) + byte + o;
-          const uint64_t d = (la.out ? (uint64_t)la.out + outo[i] : (uint64_t)p) + byte + o;
-          if (kind == DC_KIND_F64) *(g_double*)d = __builtin_fma(*(const g_double*)src, la.a, la.b);
-          else *(g_float*)d = __builtin_fmaf(*(const g_float*)src, la.af, la.bf);
+    for (int k = 0; k < U; k++) {
+      const uint64_t c = c_lo + (uint64_t)k * bs + tid;
+      if (c >= c_hi) continue;
+      const uint32_t i = find_leaf(pre, nl, c);
+      const uint64_t byte = (c - pre[i]) * kChunk;
+      const uint64_t lb = info[i] & ((1ull << kLeafKindShift) - 1);
+      const uint32_t kind = (uint32_t)(info[i] >> kLeafKindShift);
+      const uint32_t n = (uint32_t)(lb - byte < kChunk ? lb - byte : kChunk);
+      const DevPath path = t.paths[l0 + i];
+      const uint32_t es = kind == DC_KIND_F64 ? 8 : 4;
+      for (uint32_t o = 0; o + es <= n; o += es) {
+        const uint8_t* p = t.arena + path.root_off;
+        bool ok = true;
+        for (uint32_t hp = 0; hp < path.nhops && ok; hp++) {
+          const uint8_t* slot = opaque(p) + t.hops[path.hop_lo + hp];
+          ok = in_arena(t, (uint64_t)slot, 8);
+          if (ok) p = (const uint8_t*)*(const g_u64*)(uint64_t)slot;
         }
+        if (!ok || !in_arena(t, (uint64_t)p, lb)) {
+          report_wild(t.hdr);
+          break;
+        }
+        const uint64_t src = (la.src_out ? (uint64_t)la.out + outo[i] : (uint64_t)p) + byte + o;
+        const uint64_t d = (la.out ? (uint64_t)la.out + outo[i] : (uint64_t)p) + byte + o;
+        if (kind == DC_KIND_F64) *(g_double*)d = __builtin_fma(*(const g_double*)src, la.a, la.b);
+        else *(g_float*)d = __builtin_fmaf(*(const g_float*)src, la.af, la.bf);
       }
     }
   }
-  // the next tile's prologue rewrites the tables; no wait for this tile's stores
   lds_barrier();
 }
 
@@ -645,41 +710,52 @@ __global__ void __launch_bounds__(256) k_leaf_tiles(Tables t, LeafArgs la, uint6
 // array, null and unfollowed members). Nothing waits for anything: one launch
 // relocates and computes every structure.
 
-constexpr size_t kFusedLds = (size_t)(kTileMaxLeaves + 2) * 6 * 8;
+constexpr size_t kFusedLds = (size_t)(kTileMaxLeaves + 2) * 7 * 8;
 constexpr uint64_t kFirstBit = 1ull << 63;  // in the slot-offset table: this tile holds the leaf's first chunk
 
 template <int U>
 __device__ void fused_tile(const Tables& t, const LeafArgs& la, uint64_t tile, uint32_t flags, uint8_t* lds) {
   constexpr uint32_t N = kTileMaxLeaves + 2;
   uint64_t* pre = (uint64_t*)lds;
-  uint64_t* addr = pre + N;
+  uint64_t* addr = pre + N;  // the planned address, or 0: the leaf is not computed
   uint64_t* info = addr + N;
   uint64_t* outo = info + N;
   uint64_t* soff = outo + N;
   uint64_t* host = soff + N;
+  uint64_t* plan = host + N;  // the planned address (0: outside the arena)
   const bool att = (flags & DC_BATCH_ATTACH) != 0, det = (flags & DC_BATCH_DETACH) != 0;
   const int tid = threadIdx.x, bs = blockDim.x;
   const uint64_t B = (uint64_t)t.arena;
   const DevTile tl = t.tiles[tile];
   const uint32_t l0 = tl.l_lo, l1 = tl.l_hi;
   const uint32_t nl = l1 - l0 + 1;
-  for (uint32_t i = tid; i < nl; i += bs) {
-    const uint32_t l = l0 + i;
-    const uint64_t pr = t.leaf_pre[l];
+  // one leaf per thread (launches have 256 threads); until the check below,
+  // soff and host hold the slot offset and the target index
+  if (tid < (int)nl) {
+    const uint32_t l = l0 + tid;
     const uint64_t inf = t.leaf_info[l];
-    const uint64_t so = t.leaf_slot[l];
-    const uint32_t ti = t.leaf_tgt[l];
-    pre[i] = pr;
-    info[i] = inf;
-    outo[i] = t.leaf_out[l];
-    // the slot's value and the leaf's target entry in one round of loads
+    const uint64_t dev = B + t.leaf_dev[l];
+    pre[tid] = t.leaf_pre[l];
+    info[tid] = inf;
+    outo[tid] = t.leaf_out[l];
+    soff[tid] = t.leaf_slot[l];
+    host[tid] = t.leaf_tgt[l];
+    plan[tid] = in_arena(t, dev, inf & ((1ull << kLeafKindShift) - 1)) ? dev : 0;
+  }
+  if (tid == 0) pre[nl] = t.leaf_pre[l1 + 1];
+  lds_barrier();
+  // the first round's loads at the planned addresses, the only ones a leaf is computed at
+  TileRound r[U];
+  tile_round_load<U>(la, pre, plan, info, outo, nl, tl.c_lo, tl.c_hi, r);
+  // the slot's value and the leaf's target entry, while those loads are in flight
+  if (tid < (int)nl) {
+    const uint64_t so = soff[tid], dev = plan[tid];
+    const bool first = pre[tid] >= tl.c_lo;
     const bool sok = in_arena(t, B + so, 8);
     const uint64_t v = sok ? *(const g_u64*)(B + so) : 0;
-    const DevTarget tg = t.tgts[ti];
-    const bool first = pr >= tl.c_lo;
-    const uint64_t dev = B + tg.off;
+    const DevTarget tg = t.tgts[(uint32_t)host[tid]];
     uint64_t a = 0;
-    if (sok && in_arena(t, dev, inf & ((1ull << kLeafKindShift) - 1))) {
+    if (sok && dev != 0 && B + tg.off == dev) {
       // the value the slot holds before this launch touches it, and the one
       // a first tile elsewhere may already have left in it
       const uint64_t before = att ? tg.host : dev;
@@ -689,59 +765,30 @@ __device__ void fused_tile(const Tables& t, const LeafArgs& la, uint64_t tile, u
     } else {
       report_wild(t.hdr);
     }
-    addr[i] = a;
-    soff[i] = so | (first && a ? kFirstBit : 0);
-    host[i] = tg.host;
+    addr[tid] = a;
+    soff[tid] = so | (first && a ? kFirstBit : 0);
+    host[tid] = tg.host;
   }
-  if (tid == 0) pre[nl] = t.leaf_pre[l1 + 1];
   // LDS only: the attach stores need not complete before the compute
   lds_barrier();
-  for (uint64_t c_lo = tl.c_lo; c_lo < tl.c_hi; c_lo += (uint64_t)bs * U) {
-    const uint64_t c_hi = tl.c_hi;
-    Vec16 v[U];
-    uint64_t src[U], dst[U];
-    uint32_t nb[U];
-    bool f64[U];
 #pragma unroll
-    for (int k = 0; k < U; k++) {
-      const uint64_t c = c_lo + (uint64_t)k * bs + tid;
-      nb[k] = 0;
-      f64[k] = false;
-      src[k] = dst[k] = 0;
-      if (c < c_hi) {
-        const uint32_t i = find_leaf(pre, nl, c);
-        const uint64_t byte = (c - pre[i]) * kChunk;
-        const uint64_t lb = info[i] & ((1ull << kLeafKindShift) - 1);
-        f64[k] = (info[i] >> kLeafKindShift) == DC_KIND_F64;
-        nb[k] = addr[i] == 0 ? 0 : (uint32_t)(lb - byte < kChunk ? lb - byte : kChunk);
-        src[k] = (la.src_out ? (uint64_t)la.out + outo[i] : addr[i]) + byte;
-        dst[k] = (la.out ? (uint64_t)la.out + outo[i] : addr[i]) + byte;
-      }
-      if (nb[k] == kChunk) v[k].u = gload16(src[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < U; k++) {
-      if (nb[k] == kChunk) {
-        fma_chunk_any(v[k], f64[k], la);
-        gstore16(dst[k], v[k].u);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < U; k++)
-      if (nb[k] != 0 && nb[k] != kChunk) fma_partial(src[k], dst[k], nb[k], f64[k] ? DC_KIND_F64 : DC_KIND_F32, la);
+  for (int k = 0; k < U; k++)
+    if (addr[r[k].i] == 0) r[k].nb = 0;
+  tile_round_store<U>(la, addr, info, outo, r);
+  for (uint64_t c_lo = tl.c_lo + (uint64_t)bs * U; c_lo < tl.c_hi; c_lo += (uint64_t)bs * U) {
+    tile_round_load<U>(la, pre, addr, info, outo, nl, c_lo, tl.c_hi, r);
+    tile_round_store<U>(la, addr, info, outo, r);
   }
   // the first tile of each leaf writes the slot: the arena address (attach),
   // then the host address back (detach). Nothing in this launch needs the
   // attached value (every tile computes at the planned address), so both
   // stores come after the compute, by the thread that read the slot, in
   // program order
-  if (att || det)
-    for (uint32_t i = tid; i < nl; i += bs)
-      if (soff[i] & kFirstBit) {
-        g_u64* slot = (g_u64*)(B + (soff[i] & ~kFirstBit));
-        if (att) *slot = addr[i];
-        if (det) *slot = host[i];
-      }
+  if ((att || det) && tid < (int)nl && (soff[tid] & kFirstBit)) {
+    g_u64* slot = (g_u64*)(B + (soff[tid] & ~kFirstBit));
+    if (att) *slot = addr[tid];
+    if (det) *slot = host[tid];
+  }
   lds_barrier();
 }
 
@@ -780,7 +827,7 @@ __device__ void fused_resid(const Tables& t, uint64_t blk, uint32_t flags) {
 }
 
 template <int U>
-__global__ void __launch_bounds__(256) k_fused(Tables t, LeafArgs la, uint64_t ntiles, uint64_t nitems,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) k_fused(Tables t, LeafArgs la, uint64_t ntiles, uint64_t nitems,
                                                uint32_t flags) {
   __shared__ __align__(16) uint8_t lds[kFusedLds];
   for (uint64_t item = blockIdx.x; item < nitems; item += gridDim.x) {

@@ -647,6 +647,7 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     p->leaf_info.resize(nl);
     p->leaf_slot.resize(nl);
     p->leaf_out.resize(nl);
+    p->leaf_dev.resize(nl);
     each_chunk([&](int c) {
       uint64_t l = cnl[c], ch = cchunks[c], oend = 0;
       bool first = true;
@@ -662,6 +663,7 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
         p->leaf_info[l] = o.bytes | ((uint64_t)o.kind << kLeafKindShift);
         p->leaf_slot[l] = p->objs[o.parent].off + o.parent_rel;
         p->leaf_out[l] = cout[c] + ooff;
+        p->leaf_dev[l] = o.off;
         ch += (o.bytes + kChunk - 1) / kChunk;
         l++;
       }
@@ -794,6 +796,7 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     s.leaf_info = take(8 * nl);
     s.leaf_out = take(8 * nl);
     s.leaf_tgt = take(4 * nl);
+    s.leaf_dev = take(8 * nl);
     s.resid = take(sizeof(DevResid) * p->resid.size());
     s.static_end = at;
     const uint64_t max_tiles = (p->total_chunks + kTileMinChunks - 1) / kTileMinChunks +

@@ -23,6 +23,7 @@ static Tables make_tables(dc_plan p, uint8_t* arena, uint8_t* scratch) {
   t.leaf_info = (const uint64_t*)(scratch + s.leaf_info);
   t.leaf_out = (const uint64_t*)(scratch + s.leaf_out);
   t.leaf_tgt = (const uint32_t*)(scratch + s.leaf_tgt);
+  t.leaf_dev = (const uint64_t*)(scratch + s.leaf_dev);
   t.resid = (const DevResid*)(scratch + s.resid);
   t.nresid = p->resid.size();
   t.tiles = (const DevTile*)(scratch + s.tiles);
@@ -81,6 +82,7 @@ static dc_status upload_tables(dc_ctx ctx, dc_plan p, uint8_t* arena, uint8_t* s
   add(sl.leaf_info, p->leaf_info.data(), 8 * p->leaf_info.size());
   add(sl.leaf_out, p->leaf_out.data(), 8 * p->leaf_out.size());
   add(sl.leaf_tgt, p->leaf_tgt.data(), 4 * p->leaf_tgt.size());
+  add(sl.leaf_dev, p->leaf_dev.data(), 8 * p->leaf_dev.size());
   add(sl.resid, p->resid.data(), sizeof(DevResid) * p->resid.size());
   // packing is synchronous, so the header copy may live on the stack
   return upload_pieces(ctx, scratch, sl.static_end, pcs, s);
