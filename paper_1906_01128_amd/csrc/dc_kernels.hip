@@ -98,7 +98,7 @@ __host__ __device__ constexpr size_t reloc_lds_bytes(uint32_t ntypes) {
   return sizeof(RelocLds) + (size_t)ntypes * sizeof(RelocType);
 }
 
-__device__ __forceinline__ void report_bad_slot(DevHeader* hdr, uint64_t slot_off) {
+__device__ __noinline__ void report_bad_slot(DevHeader* hdr, uint64_t slot_off) {
   atomicAdd(&hdr->err_count, 1u);
   atomicCAS(&hdr->err_code, 0u, (uint32_t)kErrUnknownPtr);
   atomicMin((unsigned long long*)&hdr->err_slot, (unsigned long long)slot_off);
@@ -807,9 +807,13 @@ __device__ void fused_resid(const Tables& t, uint64_t blk, uint32_t flags) {
   g_u64* slot = (g_u64*)(B + r.slot_off);
   const uint64_t v = *slot;
   if (v == 0) return;
-  // a member left out of a selective copy reads as null on the device
+  // a member left out of a selective copy reads as null on the device (the
+  // zero is made here: the compiler would otherwise hold it from the
+  // kernel's start, spilled to scratch by every thread of the launch)
   if (!r.follow) {
-    *slot = 0;
+    uint64_t zero = 0;
+    asm volatile("" : "+v"(zero));
+    *slot = zero;
     return;
   }
   if (r.tgt == kNone) {
