@@ -515,8 +515,8 @@ __device__ __forceinline__ uint32_t find_leaf(const uint64_t* pre, uint32_t nl, 
   return lo;
 }
 
-// LDS of one compute tile: prefix, address, size|kind, image offset and
-// followed address of up to kTileMaxLeaves leaves (and one more prefix entry)
+// LDS of one compute tile: prefix, followed address, size|kind, image offset
+// and planned address of up to kTileMaxLeaves leaves (and one more prefix entry)
 constexpr size_t kTileLds = (size_t)(kTileMaxLeaves + 2) * 5 * 8;
 // a RESOLVED tile gives each of its leaves a thread of its own (launches have 256, 512 or 1024)
 static_assert(kTileMaxLeaves <= 256, "one leaf per thread in the tile prologue");
@@ -587,7 +587,7 @@ template <int U, bool DEREF>
 __device__ void leaf_tile(const Tables& t, const LeafArgs& la, uint64_t tile, uint8_t* lds) {
   constexpr uint32_t N = kTileMaxLeaves + 2;
   uint64_t* pre = (uint64_t*)lds;
-  uint64_t* addr = pre + N;   // RESOLVED: the followed address (0: wild); first the planned one
+  uint64_t* addr = pre + N;   // RESOLVED: the address the parent slot holds (0: wild)
   uint64_t* info = addr + N;
   uint64_t* outo = info + N;
   uint64_t* plan = outo + N;  // RESOLVED: the planned address (0: outside the arena)
