@@ -779,16 +779,13 @@ __device__ void fused_tile(const Tables& t, const LeafArgs& la, uint64_t tile, u
     tile_round_load<U>(la, pre, addr, info, outo, nl, c_lo, tl.c_hi, r);
     tile_round_store<U>(la, addr, info, outo, r);
   }
-  // the first tile of each leaf writes the slot: the arena address (attach),
-  // then the host address back (detach). Nothing in this launch needs the
-  // attached value (every tile computes at the planned address), so both
-  // stores come after the compute, by the thread that read the slot, in
-  // program order
-  if ((att || det) && tid < (int)nl && (soff[tid] & kFirstBit)) {
-    g_u64* slot = (g_u64*)(B + (soff[tid] & ~kFirstBit));
-    if (att) *slot = addr[tid];
-    if (det) *slot = host[tid];
-  }
+  // the first tile of each leaf writes the slot: the arena address (attach)
+  // or the host address (detach), after the compute, by the thread that read
+  // it. Nothing in this launch needs the attached value (every tile computes
+  // at the planned address), and attach and detach together leave the slot
+  // holding the host address it was checked to hold: nothing to write
+  if (att != det && tid < (int)nl && (soff[tid] & kFirstBit))
+    *(g_u64*)(B + (soff[tid] & ~kFirstBit)) = att ? addr[tid] : host[tid];
   lds_barrier();
 }
 
@@ -826,8 +823,8 @@ __device__ void fused_resid(const Tables& t, uint64_t blk, uint32_t flags) {
     report_bad_slot(t.hdr, r.slot_off);
     return;
   }
-  if (att) *slot = dev;
-  if (det) *slot = tg.host;
+  // attach and detach together leave the checked host address in place
+  if (att != det) *slot = att ? dev : tg.host;
 }
 
 template <int U>
