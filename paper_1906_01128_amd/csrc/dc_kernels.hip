@@ -604,7 +604,8 @@ __device__ void leaf_tile(const Tables& t, const LeafArgs& la, uint64_t tile, ui
       pre[tid] = t.leaf_pre[l];
       const uint64_t inf = t.leaf_info[l];
       info[tid] = inf;
-      outo[tid] = t.leaf_out[l];
+      // image offsets only for a pass that reads or writes the image
+      outo[tid] = la.out || la.src_out ? t.leaf_out[l] : 0;
       so = t.leaf_slot[l];
       lb = inf & ((1ull << kLeafKindShift) - 1);
       const uint64_t pl = B + t.leaf_dev[l];
@@ -737,7 +738,7 @@ __device__ void fused_tile(const Tables& t, const LeafArgs& la, uint64_t tile, u
     const uint64_t dev = B + t.leaf_dev[l];
     pre[tid] = t.leaf_pre[l];
     info[tid] = inf;
-    outo[tid] = t.leaf_out[l];
+    outo[tid] = la.out || la.src_out ? t.leaf_out[l] : 0;
     soff[tid] = t.leaf_slot[l];
     host[tid] = t.leaf_tgt[l];
     plan[tid] = in_arena(t, dev, inf & ((1ull << kLeafKindShift) - 1)) ? dev : 0;
