@@ -4,7 +4,9 @@ its planned address while the slot is still being read, and whatever the
 slot turns out to hold is what is computed. Here one leaf's member is
 pointed, on the device, at another leaf of the same size and kind, and the
 out-of-place image must show the other leaf's values in the first leaf's
-place (an in-place pass would update the other leaf twice, racing)."""
+place (an in-place pass would update the other leaf twice, racing). The
+kick-drift kernel is checked the same way, with two cells' position members
+swapped."""
 import numpy as np
 import pytest
 
@@ -77,3 +79,44 @@ def test_resolved_pass_follows_a_redirected_member(ctx, case):
     c.tree.check()
     assert_same_bytes(out.cpu().numpy(), want, "image with the redirected member")
     assert_same_bytes(c.device_arena(), before, "arena unchanged")
+
+
+def test_kick_drift_follows_swapped_members(ctx):
+    """Two cells of the same length have their position members swapped on
+    the device: each cell's drift lands in the other's position array, with
+    its own kicked velocity (the kernel follows the relocated members)."""
+    import oracle as orc
+    t = fx.md(seed=fx.SEED_BASE + 73, nsims=6, cells_lo=3, cells_hi=9, mean_atoms=6)
+    c = Copy(ctx, t)
+    cell, size = 1, t.types[1].size          # the MD cell: natoms@0, pos@8, vel@16, force@24
+    before = c.device_arena()
+    word = lambda buf, off: int.from_bytes(buf[off: off + 8].tobytes(), "little")
+    objs = c.oracle.objects()
+    nbytes = {int(o["off"]): int(o["bytes"]) for o in objs}
+    by_len = {}
+    for o in objs:
+        if o["kind"] == 0 and o["type"] == cell:
+            for e in range(int(o["count"])):
+                el = int(o["off"]) + e * size
+                arrays = [word(before, el + m) - c.base for m in (8, 16, 24)]
+                by_len.setdefault(nbytes[arrays[0]], []).append((el, arrays))
+    (ea, A), (eb, B) = next(v for k, v in sorted(by_len.items()) if k > 0 and len(v) >= 2)[:2]
+    n = nbytes[A[0]] // 8
+    dt, dtm = 1e-3, 1e-3 / 39.948
+    c.oracle.kick_drift(cell, 0, 1, 2, dt, dtm)
+    want = c.oracle.arena().copy()
+    f64 = lambda buf, off: buf[off: off + 8 * n].view(np.float64)
+    # the cell whose member now points at the other's positions drifts them with its own velocity
+    for pos, vel in ((B[0], A[1]), (A[0], B[1])):
+        x0, v1 = f64(before, pos).copy(), f64(want, vel)
+        f64(want, pos)[:] = [orc.fma64(float(v), dt, float(x)) for v, x in zip(v1, x0)]
+    for el, target in ((ea, B[0]), (eb, A[0])):
+        b = np.frombuffer(int(c.base + target).to_bytes(8, "little"), np.uint8).copy()
+        want[el + 8: el + 16] = b
+        c.arena[el + 8: el + 16] = torch.tensor(b, device="cuda")
+    torch.cuda.synchronize()
+    print(f"[gpu] cells at {ea} and {eb} ({n} doubles) swap their position members", flush=True)
+    c.tree.kick_drift(cell, 0, 1, 2, dt, dtm, steps=1)
+    torch.cuda.synchronize()
+    c.tree.check()
+    assert_same_bytes(c.device_arena(), want, "kick-drift with swapped members")
