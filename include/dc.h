@@ -127,6 +127,13 @@ typedef struct {
                              contiguous run of leaves, so the persistent batched
                              launch takes a whole unit per item (dc_batch_run) */
   uint64_t max_unit_leaf_bytes; /* the largest such run, in 16-byte chunks x 16 */
+  uint64_t leaf_prefix_offset;  /* byte offset in the scratch buffer of nleaves + 1
+                                   uint64 words that the deep copy computes on the
+                                   device (the sizing step of Algorithm 1, for the
+                                   leaves): word l is the number of 16-byte chunks
+                                   of the leaves before leaf l in arena order, each
+                                   leaf rounded up to whole chunks, and word nleaves
+                                   their total. Read-only for the caller. */
 } dc_plan_info;
 
 /* ---- lifecycle --------------------------------------------------------------- */

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libdc.so")
-SOURCES = ["dc_kernels.hip", "dc_host.cpp", "dc_plan.cpp", "dc_tree.cpp", "dc_chain.cpp", "dc_scalar.cpp", "dc_md.cpp", "dc_batch.cpp",
+SOURCES = ["dc_kernels.hip", "dc_scan.hip", "dc_host.cpp", "dc_plan.cpp", "dc_tree.cpp", "dc_chain.cpp", "dc_scalar.cpp", "dc_md.cpp", "dc_batch.cpp",
            "dc_server.cpp", "dc_noalloc.cpp"]
 ARCH = os.environ.get("DC_OFFLOAD_ARCH", "gfx950")
 

@@ -33,6 +33,8 @@ constexpr uint32_t kChunk = 16;             // bytes per vector access of the le
 constexpr uint32_t kTileMinChunks = 512;      // smallest tile size the scratch is sized for
 constexpr uint32_t kTileMaxChunks = 1u << 20;
 constexpr uint32_t kTileMaxLeaves = 256;
+// The device scan of the leaves' chunk prefix: blocks of kScanLeaves leaves.
+constexpr uint32_t kScanBlock = 256, kScanPer = 4, kScanLeaves = kScanBlock * kScanPer;
 
 struct DevTile {
   uint64_t c_lo, c_hi;  // chunk range
@@ -133,6 +135,7 @@ enum DevErr : uint32_t {
 struct ScratchLayout {
   uint64_t header, types, sobj, sobj_pre, segs, tgts, slot_tix;
   uint64_t leaf_slot, leaf_pre, leaf_info, leaf_out, leaf_tgt, leaf_dev, resid;
+  uint64_t leaf_pre_scan;  // per block of kScanLeaves leaves: its chunk sum, then its offset
   uint64_t tiles, paths, hops;
   uint64_t static_end;  // [0, static_end) is uploaded with every deep copy
   uint64_t total;
@@ -251,6 +254,9 @@ hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uin
 hipError_t launch_batch_units(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
                               hipStream_t s);
 hipError_t launch_reset_counters(DevHeader* hdr, hipStream_t s);
+// The leaves' 16-byte-chunk prefix (nl + 1 entries) from their size|kind
+// words, on the device; scan holds (nl + kScanLeaves - 1) / kScanLeaves + 1 words.
+hipError_t launch_leaf_prefix(const uint64_t* info, uint64_t nl, uint64_t* pre, uint64_t* scan, hipStream_t s);
 // one launch that relocates and computes: every tile translates the parent
 // slots of the leaves whose first chunk it holds (attach before its compute,
 // detach after), extra workgroups translate the other slots; no workgroup

@@ -792,13 +792,15 @@ dc_status plan_build(dc_plan p, const dc_schema_s* schema, uint32_t root_type, c
     s.tgts = take(sizeof(DevTarget) * p->tgts.size());
     s.slot_tix = take(2 * p->slot_tix.size());
     s.leaf_slot = take(8 * nl);
-    s.leaf_pre = take(8 * (nl + 1));
     s.leaf_info = take(8 * nl);
     s.leaf_out = take(8 * nl);
     s.leaf_tgt = take(4 * nl);
     s.leaf_dev = take(8 * nl);
     s.resid = take(sizeof(DevResid) * p->resid.size());
     s.static_end = at;
+    // computed on the device from the leaf sizes after each upload
+    s.leaf_pre = take(8 * (nl + 1));
+    s.leaf_pre_scan = take(8 * ((nl + kScanLeaves - 1) / kScanLeaves + 1));
     const uint64_t max_tiles = (p->total_chunks + kTileMinChunks - 1) / kTileMinChunks +
                                p->leaves.size() / (kTileMaxLeaves - 1) + 2;
     s.tiles = take(sizeof(DevTile) * max_tiles);
@@ -866,6 +868,7 @@ dc_status dc_plan_query(dc_plan p, dc_plan_info* out) {
   out->nroots = p->roots.size();
   out->unit_leaves = p->unit_leaves ? 1 : 0;
   out->max_unit_leaf_bytes = p->max_unit_leaf_chunks * kChunk;
+  out->leaf_prefix_offset = p->sl.leaf_pre;
   return DC_OK;
 }
 

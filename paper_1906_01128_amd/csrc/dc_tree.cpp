@@ -78,7 +78,6 @@ static dc_status upload_tables(dc_ctx ctx, dc_plan p, uint8_t* arena, uint8_t* s
   add(sl.tgts, p->tgts.data(), sizeof(DevTarget) * p->tgts.size());
   add(sl.slot_tix, p->slot_tix.data(), 2 * p->slot_tix.size());
   add(sl.leaf_slot, p->leaf_slot.data(), 8 * p->leaf_slot.size());
-  add(sl.leaf_pre, p->leaf_pre.data(), 8 * p->leaf_pre.size());
   add(sl.leaf_info, p->leaf_info.data(), 8 * p->leaf_info.size());
   add(sl.leaf_out, p->leaf_out.data(), 8 * p->leaf_out.size());
   add(sl.leaf_tgt, p->leaf_tgt.data(), 4 * p->leaf_tgt.size());
@@ -121,6 +120,12 @@ dc_status deep_copy(dc_ctx ctx, dc_plan p, void* d_arena, uint64_t arena_bytes, 
   uint8_t* scratch = (uint8_t*)d_scratch;
   DevHeader h;
   DC_TRY(upload_tables(ctx, p, arena, scratch, s, &h));
+  {
+    const ScratchLayout& sl = p->sl;
+    const hipError_t e = launch_leaf_prefix((const uint64_t*)(scratch + sl.leaf_info), p->leaves.size(),
+                                            (uint64_t*)(scratch + sl.leaf_pre), (uint64_t*)(scratch + sl.leaf_pre_scan), s);
+    if (e != hipSuccess) return fail(DC_E_HIP, "leaf prefix launch: %s", hipGetErrorString(e));
+  }
   DC_TRY(upload_source(ctx, arena, p->arena_bytes, arena_source(p), s));
   dc_tree t = new dc_tree_s();
   t->ctx = ctx;

@@ -72,7 +72,7 @@ OBJECT_DTYPE = np.dtype([("host", "<u8"), ("off", "<u8"), ("bytes", "<u8"), ("co
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, u64) for n in ("nobjects", "nslots", "nslots_nonnull", "nleaves", "payload_bytes", "leaf_bytes",
                                    "arena_bytes", "scratch_bytes", "out_bytes", "nsegments", "nroots",
-                                   "unit_leaves", "max_unit_leaf_bytes")]
+                                   "unit_leaves", "max_unit_leaf_bytes", "leaf_prefix_offset")]
 
 
 class KernelArgs(ctypes.Structure):

@@ -244,6 +244,24 @@ def test_batch_md_full_size(ctx, md_full, tune):
     tree.release()
 
 
+@pytest.mark.slow
+def test_leaf_prefix_md_full_size(ctx, md_full):
+    """The device's leaf chunk prefix for 7.7 M leaves (more than a thousand
+    scan blocks: block offsets in several rounds), word for word against the
+    prefix derived from the oracle's layout."""
+    from paper_1906_01128_amd import dc
+    from tests.test_gpu_leaf_prefix import device_leaf_prefix, expected_leaf_prefix
+    t, schema, plan, arena, scratch, ref = md_full
+    assert plan.info().nleaves > 1024 * 1024
+    tree = dc.Tree(ctx, plan, arena, scratch, relocate=False)
+    got = device_leaf_prefix(plan, scratch)
+    want = expected_leaf_prefix(ref.objects())
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{bad.size} words differ, first at {bad[:8]}"
+    tree.check()
+    tree.release()
+
+
 def test_forced_wait_bound_is_reported_and_the_launch_ends(ctx):
     """The persistent launch's waits are bounded. Forced (from the host) to
     wait for one item more than each phase has, every wait ends at a small
