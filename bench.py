@@ -597,7 +597,9 @@ def bench_batched(args, torch, dc):
                "one persistent launch in three phases",
             1: "three launches (relocate, every leaf, reverse relocate)",
             2: "one persistent launch in three phases",
-            3: "one fused launch: every tile relocates the slots of its own leaves"}[tune["launches"]]
+            3: "one fused launch: every tile relocates the slots of its own leaves",
+            4: "one persistent fused launch: workgroups take tiles, which relocate the slots of their own "
+               "leaves, from eight device queues"}[tune["launches"]]
     if tune["launches"] == 1:
         # the compute launch of the graph, timed as separate launches
         kname, kbytes = "k_leaf_tiles", 2 * info.leaf_bytes
@@ -614,9 +616,10 @@ def bench_batched(args, torch, dc):
         tree.detach()
         k_s = sum(ks) / len(ks)
         k_what = "k_leaf_tiles timed as separate launches beside the graph"
-    elif tune["launches"] == 3:
+    elif tune["launches"] in (3, 4):
         # the graph's one launch, timed as separate launches of the same form
-        kname, kbytes = "k_fused", step_bytes
+        # (the persistent one after its one-workgroup queue reset)
+        kname, kbytes = ("k_fused" if tune["launches"] == 3 else "k_fused_persistent"), step_bytes
         tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=tune)
         ks = []
         for _ in range(5):
@@ -627,7 +630,8 @@ def bench_batched(args, torch, dc):
             torch.cuda.synchronize()
             ks.append(e[0].elapsed_time(e[1]) / 1e3)
         k_s = sum(ks) / len(ks)
-        k_what = "k_fused (relocation and compute in one launch) timed as separate launches beside the graph"
+        k_what = (f"{kname} (relocation and compute in one launch) timed as separate launches beside the graph"
+                  + (", each after its queue reset" if tune["launches"] == 4 else ""))
     else:
         kname = "k_batch_units" if (tune["launches"] == 0 and info.unit_leaves) else "k_batch"
         kbytes, k_s = step_bytes, mean_s
@@ -710,7 +714,7 @@ def _batched_secondary(args, torch, dc, ctx, t, plan, tree, info, table):
     best = {}
     for tu, us in table:
         key = {0: "persistent_units" if info.unit_leaves else "persistent_phased", 1: "three_launches",
-               2: "persistent_phased", 3: "fused"}[tu["launches"]]
+               2: "persistent_phased", 3: "fused", 4: "persistent_fused"}[tu["launches"]]
         if key not in best or us < best[key]["us"]:
             best[key] = dict(tu, us=round(us, 1), GBps=round(step_bytes / us / 1e3, 1))
     # attach and detach alone (the relocation kernel), medians of 5

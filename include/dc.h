@@ -421,7 +421,9 @@ typedef struct {
                               launch in three phases (what 0 runs when the plan's
                               relocation units do not own contiguous leaf runs);
                               3: one fused launch of tiles that relocate their own
-                              leaves' slots (block and wg_per_cu not used) */
+                              leaves' slots (block and wg_per_cu not used); 4: the
+                              fused launch's work in one persistent launch (block
+                              256, wg_per_cu at most 8, else DC_E_INVAL) */
   uint32_t spin_limit;     /* persistent launch: polls (about 1 us each) a workgroup
                               waits for a phase to finish before it records an error
                               and goes on, so that every launch ends; 0: 2^24 */
@@ -432,7 +434,7 @@ typedef struct {
  * than its phase has, so each wait ends at its bound (keep tune->spin_limit
  * small); the launch still ends, the tree's leaf values and slots are then
  * unspecified, and the next check of the tree returns DC_E_STATE. DC_E_INVAL
- * with three launches or the fused launch (no waits to force). */
+ * with three launches or either fused launch (no waits to force). */
 enum { DC_BATCH_ATTACH = 1, DC_BATCH_DETACH = 2, DC_BATCH_FORCE_WAIT_BOUND = 4 };
 /* Every structure's relocation and its leaves' kernel (args: RESOLVED,
  * ALL_LEAVES, iters == 1), the batched use of Figure 2(d) and Algorithm 2
@@ -452,7 +454,9 @@ enum { DC_BATCH_ATTACH = 1, DC_BATCH_DETACH = 2, DC_BATCH_FORCE_WAIT_BOUND = 4 }
  * every tile computes at the leaf's planned address, the value the attach
  * writes), and
  * workgroups past the tiles translate every other slot; no workgroup waits for
- * another, and any plan can use it. ATTACH
+ * another, and any plan can use it. 4: the items of 3 in a persistent grid of
+ * wg_per_cu workgroups per compute unit that take them from eight interleaved
+ * device queues (reset by a one-workgroup kernel before the launch). ATTACH
  * requires a staged (unrelocated) tree; DETACH leaves it staged again. tune
  * NULL: the cached autotuner choice or defaults. Asynchronous on `stream`. */
 dc_status dc_batch_run(dc_tree tree, const dc_kernel_args* args, const dc_tune* tune, uint32_t flags, void* stream);

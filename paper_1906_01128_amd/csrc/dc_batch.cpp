@@ -22,9 +22,13 @@ static const dc_tune kDefaultTune = {256, 4, 1024, 1, 0};
 static const uint32_t kDefaultSpin = 1u << 24;  // polls of a persistent workgroup's wait
 
 static dc_status check_tune(const dc_tune& t) {
-  if (t.launches > 3) return fail(DC_E_INVAL, "tune.launches %u (0, 1, 2 or 3)", t.launches);
+  if (t.launches > 4) return fail(DC_E_INVAL, "tune.launches %u (0 to 4)", t.launches);
   if (t.block != 256 && t.block != 512 && t.block != 1024) return fail(DC_E_INVAL, "tune.block %u", t.block);
   if (t.wg_per_cu < 1 || t.wg_per_cu > 32) return fail(DC_E_INVAL, "tune.wg_per_cu %u", t.wg_per_cu);
+  // the persistent fused launch: 256-thread workgroups, all resident at once
+  if (t.launches == 4 && (t.block != 256 || t.wg_per_cu > 8))
+    return fail(DC_E_INVAL, "tune.launches 4 takes block 256 and at most 8 workgroups per CU (%u, %u)", t.block,
+                t.wg_per_cu);
   if (t.tile_chunks < kTileMinChunks || t.tile_chunks > kTileMaxChunks || (t.tile_chunks & (t.tile_chunks - 1)))
     return fail(DC_E_INVAL, "tune.tile_chunks %u (power of two in %u..%u)", t.tile_chunks, kTileMinChunks,
                 kTileMaxChunks);
@@ -149,6 +153,11 @@ static dc_status enqueue_batch(dc_tree t, const LeafArgs& la, const dc_tune& tu,
   } else if (tu.launches == 3) {
     // one launch: every tile relocates the slots of its own leaves
     e = launch_fused(t->tab, la, ntiles, t->tile_T, flags & (DC_BATCH_ATTACH | DC_BATCH_DETACH), s);
+  } else if (tu.launches == 4) {
+    // the same work in a persistent grid fed by device queues
+    e = launch_reset_counters(t->tab.hdr, s);
+    if (e == hipSuccess)
+      e = launch_fused_persistent(t->tab, la, ntiles, t->tile_T, flags & (DC_BATCH_ATTACH | DC_BATCH_DETACH), grid, s);
   } else if (unit_items(t, tu, flags)) {
     e = launch_reset_counters(t->tab.hdr, s);
     if (e == hipSuccess) e = launch_batch_units(t->tab, la, flags, tu.block, grid, s);
@@ -191,7 +200,7 @@ dc_status dc_batch_run(dc_tree t, const dc_kernel_args* a, const dc_tune* tune, 
   DC_TRY(batch_args(t, a, &la));
   dc_tune tu;
   DC_TRY(resolve_tune(t, tune, &tu));
-  if ((flags & DC_BATCH_FORCE_WAIT_BOUND) && (tu.launches == 1 || tu.launches == 3))
+  if ((flags & DC_BATCH_FORCE_WAIT_BOUND) && (tu.launches == 1 || tu.launches >= 3))
     return fail(DC_E_INVAL, "FORCE_WAIT_BOUND needs a launch with waits (tune.launches 0 or 2)");
   DC_HIP(hipSetDevice(t->ctx->device));
   DC_TRY(enqueue_batch(t, la, tu, flags, (hipStream_t)stream));
@@ -222,8 +231,9 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
   const uint32_t flags = DC_BATCH_ATTACH | DC_BATCH_DETACH;
   // Candidates: persistent shapes whose workgroups are all resident at once
   // (at most 2048 threads per compute unit), the per-unit form when the plan
-  // allows it, the three-phase form over several tile sizes, and three
-  // ordinary launches over several tile sizes.
+  // allows it, the three-phase form over several tile sizes, three
+  // ordinary launches and the fused launch over several tile sizes, and the
+  // persistent fused launch at four, six and eight workgroups per CU.
   std::vector<dc_tune> cands;
   const uint32_t phased = t->plan->unit_leaves ? 2u : 0u;
   for (uint32_t block : {256u, 512u, 1024u})
@@ -235,6 +245,8 @@ dc_status dc_autotune(dc_tree t, const dc_kernel_args* a, uint32_t reps, dc_tune
     }
   for (uint32_t tile : {512u, 1024u, 2048u, 4096u}) cands.push_back(dc_tune{256, 1, tile, 1, 0});
   for (uint32_t tile : {512u, 1024u, 2048u}) cands.push_back(dc_tune{256, 1, tile, 3, 0});
+  for (uint32_t wg : {4u, 6u, 8u})
+    for (uint32_t tile : {512u, 1024u, 2048u}) cands.push_back(dc_tune{256, wg, tile, 4, 0});
   clear_error();
   t->tune_table.clear();
   dc_tune best = kDefaultTune;

@@ -33,6 +33,9 @@ constexpr uint32_t kChunk = 16;             // bytes per vector access of the le
 constexpr uint32_t kTileMinChunks = 512;      // smallest tile size the scratch is sized for
 constexpr uint32_t kTileMaxChunks = 1u << 20;
 constexpr uint32_t kTileMaxLeaves = 256;
+// Work queues of the persistent fused launch: queue q hands out the items
+// q, q + kFusedQueues, ... to the workgroups whose index is q modulo it.
+constexpr uint32_t kFusedQueues = 8;
 // The device scan of the leaves' chunk prefix: blocks of kScanLeaves leaves.
 constexpr uint32_t kScanBlock = 256, kScanPer = 4, kScanLeaves = kScanBlock * kScanPer;
 
@@ -119,7 +122,11 @@ struct DevHeader {
   uint32_t pad_a[31];
   uint32_t doneB;
   uint32_t pad_b[31];
+  // the persistent fused launch's work queues, one 128-byte line each
+  uint32_t fq[kFusedQueues * 32];
 };
+// the host reads the header back into a 4 KiB pinned buffer
+static_assert(sizeof(DevHeader) <= 4096, "device header larger than its host read buffer");
 
 enum DevErr : uint32_t {
   kErrNone = 0,
@@ -254,6 +261,10 @@ hipError_t launch_batch(const Tables& t, const LeafArgs& la, uint32_t flags, uin
 hipError_t launch_batch_units(const Tables& t, const LeafArgs& la, uint32_t flags, uint32_t block, uint32_t grid,
                               hipStream_t s);
 hipError_t launch_reset_counters(DevHeader* hdr, hipStream_t s);
+// the fused launch's work in a persistent grid of `grid` 256-thread
+// workgroups taking items from kFusedQueues device queues (reset first)
+hipError_t launch_fused_persistent(const Tables& t, const LeafArgs& la, uint64_t ntiles, uint32_t tile_chunks,
+                                   uint32_t flags, uint32_t grid, hipStream_t s);
 // The leaves' 16-byte-chunk prefix (nl + 1 entries) from their size|kind
 // words, on the device; scan holds (nl + kScanLeaves - 1) / kScanLeaves + 1 words.
 hipError_t launch_leaf_prefix(const uint64_t* info, uint64_t nl, uint64_t* pre, uint64_t* scan, hipStream_t s);

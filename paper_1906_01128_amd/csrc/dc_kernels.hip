@@ -714,8 +714,13 @@ __global__ void __launch_bounds__(256) k_leaf_tiles(Tables t, LeafArgs la, uint6
 constexpr size_t kFusedLds = (size_t)(kTileMaxLeaves + 2) * 7 * 8;
 constexpr uint64_t kFirstBit = 1ull << 63;  // in the slot-offset table: this tile holds the leaf's first chunk
 
-template <int U>
-__device__ void fused_tile(const Tables& t, const LeafArgs& la, uint64_t tile, uint32_t flags, uint8_t* lds) {
+// Q: run by the persistent form, whose thread 0 publishes the workgroup's
+// next ticket (tick_val, taken before this tile's first load) in *tick_dst
+// once the first round's loads have returned, so that the ticket's return
+// never holds up a load or a barrier.
+template <int U, bool Q = false>
+__device__ void fused_tile(const Tables& t, const LeafArgs& la, uint64_t tile, uint32_t flags, uint8_t* lds,
+                           uint32_t* tick_dst = nullptr, uint32_t tick_val = 0) {
   constexpr uint32_t N = kTileMaxLeaves + 2;
   uint64_t* pre = (uint64_t*)lds;
   uint64_t* addr = pre + N;  // the planned address, or 0: the leaf is not computed
@@ -776,6 +781,7 @@ __device__ void fused_tile(const Tables& t, const LeafArgs& la, uint64_t tile, u
   for (int k = 0; k < U; k++)
     if (addr[r[k].i] == 0) r[k].nb = 0;
   tile_round_store<U>(la, addr, info, outo, r);
+  if (Q && tid == 0) *tick_dst = tick_val;
   for (uint64_t c_lo = tl.c_lo + (uint64_t)bs * U; c_lo < tl.c_hi; c_lo += (uint64_t)bs * U) {
     tile_round_load<U>(la, pre, addr, info, outo, nl, c_lo, tl.c_hi, r);
     tile_round_store<U>(la, addr, info, outo, r);
@@ -835,6 +841,52 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
   for (uint64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
     if (item < ntiles) fused_tile<U>(t, la, item, flags, lds);
     else fused_resid(t, item - ntiles, flags);
+  }
+}
+
+// The same items in a persistent grid. A grid-stride loop lets the
+// workgroups drift apart over the arena, which HBM serves more slowly than
+// the compact, advancing window of one item per workgroup in dispatch order;
+// taking items from a queue keeps that window. One queue is bound by its
+// atomic's throughput (on a flat 12 GiB stream of 16 KB tiles, 2.8 TB/s), so
+// there are kFusedQueues of them, interleaved: the workgroup with index b
+// takes tickets from queue q = b mod kFusedQueues, and ticket k names item
+// k * kFusedQueues + q (the items the dispatcher would send to the same
+// XCD). Every item is taken exactly once and no workgroup waits for another,
+// so the launch ends whatever the order. The queues are reset before each
+// launch (launch_reset_counters).
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+__device__ __forceinline__ uint32_t ticket(uint64_t ctr) {
+  return __hip_atomic_fetch_add((g_u32*)ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int U>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_fused_persistent(Tables t, LeafArgs la, uint64_t ntiles, uint64_t nitems, uint32_t flags) {
+  __shared__ __align__(16) uint8_t lds[kFusedLds];
+  __shared__ uint32_t tick[2];
+  const uint32_t q = blockIdx.x % kFusedQueues;
+  // The address passes through an empty asm so that the compiler takes it for
+  // a per-lane value: for a wave-uniform address it would combine the wave's
+  // atomics into one and wait for its return right away to share it out.
+  // (A global, not a generic, address: a generic atomic would also hold up
+  // every wait for LDS until it returns.)
+  uint64_t ctr = (uint64_t)&t.hdr->fq[q * 32];
+  asm volatile("" : "+v"(ctr));
+  if (threadIdx.x == 0) tick[0] = ticket(ctr);
+  lds_barrier();
+  for (uint32_t cur = 0;; cur ^= 1) {
+    const uint64_t item = (uint64_t)tick[cur] * kFusedQueues + q;
+    if (item >= nitems) break;
+    uint32_t next = 0;
+    if (threadIdx.x == 0) next = ticket(ctr);
+    if (item < ntiles) {
+      fused_tile<U, true>(t, la, item, flags, lds, &tick[cur ^ 1], next);
+    } else {
+      fused_resid(t, item - ntiles, flags);
+      if (threadIdx.x == 0) tick[cur ^ 1] = next;
+      lds_barrier();
+    }
   }
 }
 
@@ -1151,6 +1203,7 @@ __global__ void k_reset_counters(DevHeader* hdr) {
     hdr->doneA = 0;
     hdr->doneB = 0;
   }
+  if (threadIdx.x < kFusedQueues) hdr->fq[threadIdx.x * 32] = 0;
 }
 
 }  // namespace
@@ -1336,6 +1389,21 @@ hipError_t launch_fused(const Tables& t, const LeafArgs& la, uint64_t ntiles, ui
     hipLaunchKernelGGL((k_fused<2>), dim3((uint32_t)grid), dim3(256), 0, s, t, la, ntiles, nitems, flags);
   else
     hipLaunchKernelGGL((k_fused<4>), dim3((uint32_t)grid), dim3(256), 0, s, t, la, ntiles, nitems, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_persistent(const Tables& t, const LeafArgs& la, uint64_t ntiles, uint32_t tile_chunks,
+                                   uint32_t flags, uint32_t grid, hipStream_t s) {
+  const uint64_t nitems = ntiles + (t.nresid + 255) / 256;
+  if (nitems == 0) return hipSuccess;
+  // every queue needs a workgroup: its items are taken by no other
+  if (grid < kFusedQueues) grid = kFusedQueues;
+  // tickets are 32-bit
+  if (nitems / kFusedQueues >= 0xffffffffull - grid) return hipErrorInvalidValue;
+  if (tile_chunks <= 512)
+    hipLaunchKernelGGL((k_fused_persistent<2>), dim3(grid), dim3(256), 0, s, t, la, ntiles, nitems, flags);
+  else
+    hipLaunchKernelGGL((k_fused_persistent<4>), dim3(grid), dim3(256), 0, s, t, la, ntiles, nitems, flags);
   return hipGetLastError();
 }
 

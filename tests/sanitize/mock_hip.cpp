@@ -272,4 +272,7 @@ hipError_t launch_batch_units(const Tables&, const LeafArgs&, uint32_t, uint32_t
 hipError_t launch_reset_counters(DevHeader*, hipStream_t s) { return launch(s); }
 hipError_t launch_leaf_prefix(const uint64_t*, uint64_t, uint64_t*, uint64_t*, hipStream_t s) { return launch(s); }
 hipError_t launch_fused(const Tables&, const LeafArgs&, uint64_t, uint32_t, uint32_t, hipStream_t s) { return launch(s); }
+hipError_t launch_fused_persistent(const Tables&, const LeafArgs&, uint64_t, uint32_t, uint32_t, uint32_t, hipStream_t s) {
+  return launch(s);
+}
 }  // namespace dc

@@ -52,7 +52,11 @@ SHAPES = [None,
           # three launches
           dict(tile_chunks=1024, launches=1), dict(tile_chunks=4096, launches=1),
           # one fused launch: tiles relocate their own leaves' slots
-          dict(tile_chunks=512, launches=3), dict(tile_chunks=1024, launches=3), dict(tile_chunks=65536, launches=3)]
+          dict(tile_chunks=512, launches=3), dict(tile_chunks=1024, launches=3), dict(tile_chunks=65536, launches=3),
+          # the fused launch's items in a persistent grid fed by device queues
+          dict(block=256, wg_per_cu=8, tile_chunks=512, launches=4),
+          dict(block=256, wg_per_cu=4, tile_chunks=1024, launches=4),
+          dict(block=256, wg_per_cu=1, tile_chunks=65536, launches=4)]
 
 
 @pytest.mark.parametrize("tune", SHAPES)
@@ -66,14 +70,14 @@ def test_batch_attach_detach_any_tile_shape(ctx, tune):
     c.tree.check()
 
 
-@pytest.mark.parametrize("launches", [0, 1, 2, 3])
+@pytest.mark.parametrize("launches", [0, 1, 2, 3, 4])
 def test_batch_each_flag_combination(ctx, launches):
     """ATTACH alone, then neither (compute on the attached tree), then DETACH
     alone, each compared with the oracle's arena at that point: attached and
     advanced one pass, two passes, then staged again after three."""
     t = fx.md(seed=15, nsims=80, cells_lo=1, cells_hi=60, mean_atoms=7)
     c = Copy(ctx, t, relocate=False)
-    tune = dict(block=512, wg_per_cu=2, tile_chunks=2048, launches=launches)
+    tune = dict(block=256 if launches == 4 else 512, wg_per_cu=2, tile_chunks=2048, launches=launches)
     ref = c.oracle
     c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=False, tune=tune)
     ref.run_kernel(1.0001, 0.5, iters=1, select="all")
@@ -100,13 +104,15 @@ def test_batch_units_not_contiguous(ctx, launches):
 
 
 @pytest.mark.parametrize("tune", [dict(block=256, wg_per_cu=1, launches=0),
-                                  dict(block=256, wg_per_cu=1, tile_chunks=4096, launches=2)])
+                                  dict(block=256, wg_per_cu=1, tile_chunks=4096, launches=2),
+                                  dict(block=256, wg_per_cu=1, tile_chunks=1024, launches=4)])
 def test_batch_many_items_per_workgroup(ctx, tune):
     """600 simulations (~0.7 GB) on one 256-thread workgroup per compute unit:
     every workgroup takes several relocation units (per-unit form), or, in
     three phases, several relocation units and then some twenty batches of
     two compute tiles each, with its phase waits contended by every other
-    workgroup. The whole arena is compared with the oracle."""
+    workgroup, or (persistent fused) some 170 tiles from its queue. The whole
+    arena is compared with the oracle."""
     fx.set_threads(0)
     t = fx.md(seed=21, nsims=600)
     c = Copy(ctx, t, relocate=False)
@@ -131,7 +137,7 @@ def test_batch_wide_and_out_of_place(ctx):
     assert_same_bytes(c.device_arena(), c.oracle.arena(), "arena relocated, leaves untouched")
 
 
-@pytest.mark.parametrize("launches", [0, 1, 3])
+@pytest.mark.parametrize("launches", [0, 1, 3, 4])
 def test_graph_replays(ctx, launches):
     t = fx.md(seed=6, nsims=40, cells_lo=2, cells_hi=30, mean_atoms=8)
     c = Copy(ctx, t, relocate=False)
@@ -147,7 +153,7 @@ def test_graph_replays(ctx, launches):
     g.close()
 
 
-@pytest.mark.parametrize("launches", [0, 1])
+@pytest.mark.parametrize("launches", [0, 1, 4])
 def test_graph_replay_after_another_tile_size(ctx, launches):
     """A graph replays the tile count it was captured with: calls with other
     tile sizes in between rebuild the tree's tile list, and the replay must
@@ -183,11 +189,13 @@ def test_autotune_then_parity(ctx, tmp_path, monkeypatch):
     t = fx.md(seed=8, nsims=200, cells_lo=4, cells_hi=64, mean_atoms=16)
     c = Copy(ctx, t, relocate=False)
     choice = c.tree.autotune(reps=1)
-    assert choice["block"] in (256, 512, 1024) and choice["launches"] in (0, 1, 2, 3)
+    assert choice["block"] in (256, 512, 1024) and choice["launches"] in (0, 1, 2, 3, 4)
     table = c.tree.autotune_results()
     assert len(table) >= 8 and choice in [tu for tu, _ in table]
     assert all(tu["block"] * tu["wg_per_cu"] <= 2048 for tu, _ in table if tu["launches"] in (0, 2))
     assert any(tu["launches"] == 3 for tu, _ in table)
+    assert all(tu["block"] == 256 and tu["wg_per_cu"] <= 8 for tu, _ in table if tu["launches"] == 4)
+    assert {tu["wg_per_cu"] for tu, _ in table if tu["launches"] == 4} == {4, 6, 8}
     assert any(tu["block"] == 1024 for tu, _ in table)
     assert (tmp_path / "tune.json").exists()
     # the autotuner changed leaf values; copy again and run with the cached choice
@@ -221,7 +229,9 @@ def md_full(ctx):
 @pytest.mark.parametrize("tune", [dict(block=1024, wg_per_cu=2, launches=0),
                                   dict(block=1024, wg_per_cu=2, tile_chunks=16384, launches=2),
                                   dict(tile_chunks=1024, launches=1),
-                                  dict(tile_chunks=1024, launches=3)])
+                                  dict(tile_chunks=1024, launches=3),
+                                  dict(block=256, wg_per_cu=8, tile_chunks=1024, launches=4),
+                                  dict(block=256, wg_per_cu=4, tile_chunks=2048, launches=4)])
 def test_batch_md_full_size(ctx, md_full, tune):
     """10,000 simulations, ~7.8 M arrays, ~12 GB, in each batched form with
     an explicit shape (the per-unit persistent launch, the three-phase
@@ -278,14 +288,36 @@ def test_forced_wait_bound_is_reported_and_the_launch_ends(ctx):
         c.tree.check()
     assert e.value.name == "STATE" and "wait bound" in str(e.value)
     c2 = Copy(ctx, t, relocate=False)
-    # three launches have no waits to force
-    with pytest.raises(dc.DcError) as e:
-        c2.tree.batch_run(attach=True, detach=True, tune=dict(tile_chunks=1024, launches=1), force_wait_bound=True)
-    assert e.value.name == "INVAL"
+    # three launches and the fused ones have no waits to force
+    for bad in (dict(tile_chunks=1024, launches=1), dict(tile_chunks=1024, launches=3),
+                dict(block=256, wg_per_cu=4, tile_chunks=1024, launches=4)):
+        with pytest.raises(dc.DcError) as e:
+            c2.tree.batch_run(attach=True, detach=True, tune=bad, force_wait_bound=True)
+        assert e.value.name == "INVAL"
     want = _staged_after_kernel(c2, 1)
     c2.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=dict(tune, spin_limit=0))
     assert_same_bytes(c2.device_arena(), want, "persistent launch after a forced wait bound")
     c2.tree.check()
+
+
+def test_persistent_fused_shape_is_checked(ctx):
+    """The persistent fused launch takes 256-thread workgroups, at most eight
+    per compute unit (all resident at once); other shapes are refused before
+    anything is enqueued, and the tree then runs as before."""
+    from paper_1906_01128_amd import dc
+    t = fx.md(seed=5, nsims=20, cells_lo=1, cells_hi=20, mean_atoms=5)
+    c = Copy(ctx, t, relocate=False)
+    for bad in (dict(block=512, wg_per_cu=2, tile_chunks=1024, launches=4),
+                dict(block=256, wg_per_cu=9, tile_chunks=1024, launches=4),
+                dict(block=256, wg_per_cu=4, tile_chunks=1024, launches=5)):
+        with pytest.raises(dc.DcError) as e:
+            c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=bad)
+        assert e.value.name == "INVAL", bad
+    want = _staged_after_kernel(c, 1)
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True,
+                     tune=dict(block=256, wg_per_cu=8, tile_chunks=1024, launches=4))
+    assert_same_bytes(c.device_arena(), want, "persistent fused after refused shapes")
+    c.tree.check()
 
 
 def test_autotune_and_graph_right_after_staging(ctx, tmp_path, monkeypatch):
@@ -327,9 +359,13 @@ def test_autotune_and_graph_right_after_staging(ctx, tmp_path, monkeypatch):
     ref.free()
 
 
+FUSED = [dict(tile_chunks=512, launches=3), dict(block=256, wg_per_cu=2, tile_chunks=512, launches=4)]
+
+
 @pytest.mark.parametrize("seed", range(8))
 @pytest.mark.parametrize("detach", [False, True])
-def test_fused_random_graphs(ctx, seed, detach):
+@pytest.mark.parametrize("fused", FUSED, ids=["fused", "persistent"])
+def test_fused_random_graphs(ctx, seed, detach, fused):
     """The fused launch on random pointer graphs: null members, arrays reached
     twice (the second slot is translated apart from the tiles), cycles,
     zero-length arrays and struct arrays, several roots; 512-chunk tiles so
@@ -337,26 +373,27 @@ def test_fused_random_graphs(ctx, seed, detach):
     t = fx.random_tree(5100 + seed, max_objects=80, nroots=1 + seed % 3)
     c = Copy(ctx, t, align=[16, 64, 256][seed % 3], relocate=False)
     ref = c.oracle
-    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=detach, tune=dict(tile_chunks=512, launches=3))
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=detach, tune=fused)
     ref.run_kernel(1.0001, 0.5, iters=1, select="all")
     if detach:
         assert_same_bytes(c.device_arena(), _staged_after_kernel(c, 1), f"fused attach+detach seed {seed}")
     else:
         assert_same_bytes(c.device_arena(), ref.arena(), f"fused attach seed {seed}")
         # and detach alone afterwards, with one more pass
-        c.tree.batch_run(a=1.0001, b=0.5, attach=False, detach=True, tune=dict(tile_chunks=512, launches=3))
+        c.tree.batch_run(a=1.0001, b=0.5, attach=False, detach=True, tune=fused)
         assert_same_bytes(c.device_arena(), _staged_after_kernel(c, 2), f"fused detach seed {seed}")
     c.tree.check()
 
 
-def test_fused_selective_and_long_leaves(ctx):
+@pytest.mark.parametrize("fused", FUSED, ids=["fused", "persistent"])
+def test_fused_selective_and_long_leaves(ctx, fused):
     """A selective copy (unfollowed members are zeroed, apart from the
     tiles) and leaves of up to 40,000 elements spread over many 512-chunk
     tiles, compared with the oracle after attach, and after attach + detach."""
     t = fx.wide(seed=91, f1=6, f2=9, lo=1, hi=40000)
     follow = [0b1, 0b1, 0b01]   # the leaf structs follow their f32 member only
     c = Copy(ctx, t, relocate=False, follow=follow)
-    c.tree.batch_run(a=0.9999, b=-0.25, attach=True, detach=False, tune=dict(tile_chunks=512, launches=3))
+    c.tree.batch_run(a=0.9999, b=-0.25, attach=True, detach=False, tune=fused)
     c.oracle.run_kernel(0.9999, -0.25, iters=1, select="all")
-    assert_same_bytes(c.device_arena(), c.oracle.arena(), "fused selective attach")
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), f"fused selective attach {fused}")
     c.tree.check()
