@@ -855,9 +855,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
 // XCD). Every item is taken exactly once and no workgroup waits for another,
 // so the launch ends whatever the order. The queues are reset before each
 // launch (launch_reset_counters).
+// One ticket from a queue: an atomic increment (wrapping at 2^32), which,
+// unlike an atomic add, the compiler leaves as it is written; for an add to
+// a wave-uniform address it would combine the wave's atomics into one and
+// wait for its return at once to share it out. A global (not generic)
+// address, so that the atomic does not hold up waits for LDS.
 typedef __attribute__((address_space(1))) uint32_t g_u32;
-__device__ __forceinline__ uint32_t ticket(uint64_t ctr) {
-  return __hip_atomic_fetch_add((g_u32*)ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint32_t ticket(DevHeader* hdr, uint32_t q) {
+  // the queue's offset passes through an empty asm where it is used, so that
+  // its address is formed there in scalar registers: hoisted out of the item
+  // loop, the compiler keeps a vector copy of it spilled to scratch, whose
+  // reload waits for every store the wave has in flight
+  uint32_t off = q * 32 * (uint32_t)sizeof(uint32_t);
+  asm volatile("" : "+s"(off));
+  return __builtin_amdgcn_atomic_inc32((g_u32*)((uint8_t*)hdr->fq + off), 0xffffffffu, __ATOMIC_RELAXED, "agent");
 }
 
 template <int U>
@@ -866,20 +877,15 @@ k_fused_persistent(Tables t, LeafArgs la, uint64_t ntiles, uint64_t nitems, uint
   __shared__ __align__(16) uint8_t lds[kFusedLds];
   __shared__ uint32_t tick[2];
   const uint32_t q = blockIdx.x % kFusedQueues;
-  // The address passes through an empty asm so that the compiler takes it for
-  // a per-lane value: for a wave-uniform address it would combine the wave's
-  // atomics into one and wait for its return right away to share it out.
-  // (A global, not a generic, address: a generic atomic would also hold up
-  // every wait for LDS until it returns.)
-  uint64_t ctr = (uint64_t)&t.hdr->fq[q * 32];
-  asm volatile("" : "+v"(ctr));
-  if (threadIdx.x == 0) tick[0] = ticket(ctr);
+  if (threadIdx.x == 0) tick[0] = ticket(t.hdr, q);
   lds_barrier();
   for (uint32_t cur = 0;; cur ^= 1) {
-    const uint64_t item = (uint64_t)tick[cur] * kFusedQueues + q;
+    // the same for every thread: taken as a scalar, so the item's descriptor
+    // is a scalar load, which no earlier vector store holds up
+    const uint64_t item = (uint64_t)__builtin_amdgcn_readfirstlane(tick[cur]) * kFusedQueues + q;
     if (item >= nitems) break;
-    uint32_t next = 0;
-    if (threadIdx.x == 0) next = ticket(ctr);
+    uint32_t next;  // meaningful in thread 0, the only one that publishes it
+    if (threadIdx.x == 0) next = ticket(t.hdr, q);
     if (item < ntiles) {
       fused_tile<U, true>(t, la, item, flags, lds, &tick[cur ^ 1], next);
     } else {
