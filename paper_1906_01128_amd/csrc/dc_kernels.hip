@@ -715,12 +715,12 @@ constexpr size_t kFusedLds = (size_t)(kTileMaxLeaves + 2) * 7 * 8;
 constexpr uint64_t kFirstBit = 1ull << 63;  // in the slot-offset table: this tile holds the leaf's first chunk
 
 // Q: run by the persistent form, whose thread 0 publishes the workgroup's
-// next ticket (tick_val, taken before this tile's first load) in *tick_dst
+// next ticket (*tick_src, taken before this tile's first load) in *tick_dst
 // once the first round's loads have returned, so that the ticket's return
-// never holds up a load or a barrier.
+// never holds up a load or a barrier. Only thread 0 reads *tick_src.
 template <int U, bool Q = false>
 __device__ void fused_tile(const Tables& t, const LeafArgs& la, uint64_t tile, uint32_t flags, uint8_t* lds,
-                           uint32_t* tick_dst = nullptr, uint32_t tick_val = 0) {
+                           uint32_t* tick_dst = nullptr, const uint32_t* tick_src = nullptr) {
   constexpr uint32_t N = kTileMaxLeaves + 2;
   uint64_t* pre = (uint64_t*)lds;
   uint64_t* addr = pre + N;  // the planned address, or 0: the leaf is not computed
@@ -781,7 +781,7 @@ __device__ void fused_tile(const Tables& t, const LeafArgs& la, uint64_t tile, u
   for (int k = 0; k < U; k++)
     if (addr[r[k].i] == 0) r[k].nb = 0;
   tile_round_store<U>(la, addr, info, outo, r);
-  if (Q && tid == 0) *tick_dst = tick_val;
+  if (Q && tid == 0) *tick_dst = *tick_src;
   for (uint64_t c_lo = tl.c_lo + (uint64_t)bs * U; c_lo < tl.c_hi; c_lo += (uint64_t)bs * U) {
     tile_round_load<U>(la, pre, addr, info, outo, nl, c_lo, tl.c_hi, r);
     tile_round_store<U>(la, addr, info, outo, r);
@@ -866,9 +866,9 @@ __device__ __forceinline__ uint32_t ticket(DevHeader* hdr, uint32_t q) {
   // its address is formed there in scalar registers: hoisted out of the item
   // loop, the compiler keeps a vector copy of it spilled to scratch, whose
   // reload waits for every store the wave has in flight
-  uint32_t off = q * 32 * (uint32_t)sizeof(uint32_t);
-  asm volatile("" : "+s"(off));
-  return __builtin_amdgcn_atomic_inc32((g_u32*)((uint8_t*)hdr->fq + off), 0xffffffffu, __ATOMIC_RELAXED, "agent");
+  uint32_t w = q * 32;  // the queue's first word in hdr->fq
+  asm volatile("" : "+s"(w));
+  return __builtin_amdgcn_atomic_inc32((g_u32*)(hdr->fq + w), 0xffffffffu, __ATOMIC_RELAXED, "agent");
 }
 
 template <int U>
@@ -884,10 +884,13 @@ k_fused_persistent(Tables t, LeafArgs la, uint64_t ntiles, uint64_t nitems, uint
     // is a scalar load, which no earlier vector store holds up
     const uint64_t item = (uint64_t)__builtin_amdgcn_readfirstlane(tick[cur]) * kFusedQueues + q;
     if (item >= nitems) break;
-    uint32_t next;  // meaningful in thread 0, the only one that publishes it
+    // Set and read by thread 0 only. Setting it in the other threads too would
+    // make the whole wave wait, before every item, for the register the last
+    // ticket returned into, and with it for every store the wave has in flight.
+    uint32_t next;
     if (threadIdx.x == 0) next = ticket(t.hdr, q);
     if (item < ntiles) {
-      fused_tile<U, true>(t, la, item, flags, lds, &tick[cur ^ 1], next);
+      fused_tile<U, true>(t, la, item, flags, lds, &tick[cur ^ 1], &next);
     } else {
       fused_resid(t, item - ntiles, flags);
       if (threadIdx.x == 0) tick[cur ^ 1] = next;
