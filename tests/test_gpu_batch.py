@@ -124,6 +124,34 @@ def test_batch_many_items_per_workgroup(ctx, tune):
     c.tree.check()
 
 
+SMALL = {
+    "no leaves": lambda: fx.linear(k=3, n=0),
+    "one leaf of one element": lambda: fx.linear(k=2, n=1),
+    "plain, 16 leaves": lambda: fx.plain(),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("tune", [dict(tile_chunks=512, launches=3),
+                                  dict(block=256, wg_per_cu=8, tile_chunks=512, launches=4),
+                                  dict(block=256, wg_per_cu=1, tile_chunks=1024, launches=4)],
+                         ids=["fused", "persistent8", "persistent1"])
+def test_fused_forms_on_small_trees(ctx, name, tune):
+    """Trees with fewer items than the persistent grid has queues or
+    workgroups (most queues hand out nothing), no leaves at all, a single
+    one-element leaf: attach + pass + detach, then attach + pass, each
+    compared with the oracle."""
+    t = SMALL[name]()
+    c = Copy(ctx, t, relocate=False)
+    want = _staged_after_kernel(c, 1)
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=True, tune=tune)
+    assert_same_bytes(c.device_arena(), want, f"{name} attach+detach {tune}")
+    c.tree.batch_run(a=1.0001, b=0.5, attach=True, detach=False, tune=tune)
+    c.oracle.run_kernel(1.0001, 0.5, iters=2, select="all")
+    assert_same_bytes(c.device_arena(), c.oracle.arena(), f"{name} attach {tune}")
+    c.tree.check()
+
+
 def test_batch_wide_and_out_of_place(ctx):
     t = fx.wide(seed=81, f1=16, f2=16, lo=1, hi=5000)
     c = Copy(ctx, t, relocate=False)
