@@ -273,6 +273,72 @@ static int run_copy() {
   return 0;
 }
 
+// The batched form's host logic: every form enqueues on a staged MD tree (the
+// stand-in kernels compute nothing), shapes each form cannot take are
+// refused before anything is enqueued, and the autotuner's candidate list
+// holds the persistent fused launch at four, six and eight workgroups per CU.
+static int run_batch() {
+  fx_set_threads(2);
+  dc_ctx ctx = nullptr;
+  CHECK(dc_ctx_create(0, &ctx) == DC_OK, "ctx: %s", dc_last_error());
+  Tree a(FX_SHAPE_MD, 71, {200, 4, 64, 24});
+  dc_schema s = make_schema(a.t);
+  dc_plan p = nullptr;
+  uint64_t ab = 0, sb = 0;
+  CHECK(dc_plan_create(ctx, s, a.t->root_type, (const void* const*)a.t->roots, a.t->nroots, 64, &p, &ab, &sb) == DC_OK,
+        "plan: %s", dc_last_error());
+  void *arena = nullptr, *scratch = nullptr;
+  CHECK(hipMalloc(&arena, ab) == hipSuccess && hipMalloc(&scratch, sb) == hipSuccess, "device buffers");
+  dc_tree tree = nullptr;
+  CHECK(dc_stage_to_device(ctx, p, arena, ab, scratch, sb, nullptr, &tree) == DC_OK, "stage: %s", dc_last_error());
+  dc_kernel_args ka{};
+  ka.mode = DC_MODE_RESOLVED;
+  ka.select = DC_SELECT_ALL_LEAVES;
+  ka.iters = 1;
+  ka.a = 1.0001;
+  ka.b = 0.5;
+  const uint32_t both = DC_BATCH_ATTACH | DC_BATCH_DETACH;
+  const dc_tune good[] = {{256, 4, 1024, 0, 0}, {256, 1, 1024, 1, 0}, {512, 2, 4096, 2, 0},
+                          {256, 1, 512, 3, 0},  {256, 8, 1024, 4, 0}, {256, 4, 2048, 4, 0}};
+  for (const dc_tune& tu : good)
+    CHECK(dc_batch_run(tree, &ka, &tu, both, nullptr) == DC_OK, "launches %u block %u x %u: %s", tu.launches, tu.block,
+          tu.wg_per_cu, dc_last_error());
+  const dc_tune bad[] = {{512, 2, 1024, 4, 0}, {256, 9, 1024, 4, 0}, {256, 4, 1024, 5, 0}, {256, 4, 1000, 3, 0}};
+  for (const dc_tune& tu : bad)
+    CHECK(dc_batch_run(tree, &ka, &tu, both, nullptr) == DC_E_INVAL, "launches %u block %u x %u tile %u accepted",
+          tu.launches, tu.block, tu.wg_per_cu, tu.tile_chunks);
+  for (uint32_t l : {1u, 3u, 4u}) {
+    const dc_tune tu{256, 4, 1024, l, 0};
+    CHECK(dc_batch_run(tree, &ka, &tu, both | DC_BATCH_FORCE_WAIT_BOUND, nullptr) == DC_E_INVAL,
+          "forced wait bound accepted with launches %u", l);
+  }
+  dc_tune best{};
+  CHECK(dc_autotune(tree, &ka, 1, &best) == DC_OK, "autotune: %s", dc_last_error());
+  uint32_t n = 0;
+  CHECK(dc_autotune_results(tree, nullptr, nullptr, 0, &n) == DC_OK && n > 0, "autotune results");
+  std::vector<dc_tune> tunes(n);
+  std::vector<double> us(n);
+  CHECK(dc_autotune_results(tree, tunes.data(), us.data(), n, &n) == DC_OK, "autotune results");
+  int persistent_fused = 0;
+  for (const dc_tune& tu : tunes) {
+    CHECK(tu.launches > 2 || tu.launches == 1 || tu.block * tu.wg_per_cu <= 2048, "candidate over 2048 threads per CU");
+    if (tu.launches == 4) {
+      persistent_fused++;
+      CHECK(tu.block == 256 && (tu.wg_per_cu == 4 || tu.wg_per_cu == 6 || tu.wg_per_cu == 8), "persistent fused %u x %u",
+            tu.block, tu.wg_per_cu);
+    }
+  }
+  CHECK(persistent_fused == 9, "%d persistent fused candidates", persistent_fused);
+  CHECK(dc_tree_check(tree, nullptr) == DC_OK, "check");
+  CHECK(dc_tree_release(tree) == DC_OK, "release");
+  (void)hipFree(arena);
+  (void)hipFree(scratch);
+  dc_plan_destroy(p);
+  dc_schema_destroy(s);
+  dc_ctx_destroy(ctx);
+  return 0;
+}
+
 // Jobs from `nthreads` submitting threads on one server, each waiting for
 // its own jobs; keys shared between threads, a budget small enough to evict.
 static int run_server(int nthreads, int jobs_per_thread, uint32_t fail_copy_at) {
@@ -361,6 +427,7 @@ int main(int argc, char** argv) {
     const std::string m = argv[i];
     if (m == "plan") run_plan();
     else if (m == "copy") run_copy();
+    else if (m == "batch") run_batch();
     else if (m == "server") {
       run_server(1, 12, 0);
       run_server(4, 16, 0);

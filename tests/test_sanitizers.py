@@ -1,8 +1,8 @@
 """The host library and the CPU oracle under sanitizers, on the CPU.
 
 tests/sanitize/host_checks.cpp drives the planner against the oracle, the deep
-copy and copy back through the pinned staging ring, and the served form from
-several submitting threads; tests/sanitize/mock_hip.cpp stands in for the HIP
+copy and copy back through the pinned staging ring, the batched form's shape
+checks and autotuner, and the served form from several submitting threads; tests/sanitize/mock_hip.cpp stands in for the HIP
 runtime (host memory as device memory, one worker thread per stream, so
 copies and event records really run asynchronously to their callers).
 
@@ -61,9 +61,10 @@ def _run(exe, modes, env):
 def test_address_and_undefined_behaviour(tmp_path):
     exe = _build(str(tmp_path / "asan"), "gcc", "g++",
                  ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"])
-    out = _run(exe, ["plan", "copy", "server"], {"ASAN_OPTIONS": "detect_leaks=1:abort_on_error=0",
-                                                  "UBSAN_OPTIONS": "print_stacktrace=1"})
-    assert "plan: 0 failures" in out and "copy: 0 failures" in out and "server: 0 failures" in out, out
+    out = _run(exe, ["plan", "copy", "batch", "server"], {"ASAN_OPTIONS": "detect_leaks=1:abort_on_error=0",
+                                                           "UBSAN_OPTIONS": "print_stacktrace=1"})
+    for mode in ("plan", "copy", "batch", "server"):
+        assert f"{mode}: 0 failures" in out, out
 
 
 @pytest.mark.skipif(not os.path.exists(os.path.join(LLVM, "clang++")) or not os.path.isdir("/opt/rocm/include"),
@@ -71,5 +72,6 @@ def test_address_and_undefined_behaviour(tmp_path):
 def test_threads(tmp_path):
     exe = _build(str(tmp_path / "tsan"), os.path.join(LLVM, "clang"), os.path.join(LLVM, "clang++"),
                  ["-fsanitize=thread"])
-    out = _run(exe, ["copy", "server"], {"TSAN_OPTIONS": "halt_on_error=1:second_deadlock_stack=1"})
-    assert "copy: 0 failures" in out and "server: 0 failures" in out, out
+    out = _run(exe, ["copy", "batch", "server"], {"TSAN_OPTIONS": "halt_on_error=1:second_deadlock_stack=1"})
+    for mode in ("copy", "batch", "server"):
+        assert f"{mode}: 0 failures" in out, out
