@@ -493,6 +493,15 @@ dc_status dc_autotune_results(dc_tree tree, dc_tune* tunes, double* us, uint32_t
 dc_status dc_graph_create(dc_tree tree, const dc_kernel_args* args, const dc_tune* tune, uint32_t flags,
                           int upload, int download, dc_graph* out);
 dc_status dc_graph_launch(dc_graph graph, void* stream);
+/* The page-locked host buffer a graph captured with download != 0 transfers
+ * the arena into (Algorithm 2 step 5's transfer back, as a graph node):
+ * *host and *bytes (the arena's size). The buffer belongs to the graph and
+ * lives until dc_graph_destroy; after a replay has completed on its stream
+ * it holds the arena as that replay left it (device addresses in the slots
+ * only if the tree was left attached, which a graph never does). Errors:
+ * DC_E_INVAL for a NULL argument, DC_E_STATE for a graph captured without
+ * download. */
+dc_status dc_graph_image(dc_graph graph, const void** host, uint64_t* bytes);
 /* Destroys a graph (before its tree is released). */
 dc_status dc_graph_destroy(dc_graph graph);
 

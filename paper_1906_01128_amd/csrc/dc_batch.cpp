@@ -189,6 +189,7 @@ struct dc_graph_s {
   hipGraphExec_t exec = nullptr;
   uint8_t* up = nullptr;    // pinned staged image
   uint8_t* down = nullptr;  // pinned arena copy
+  uint64_t bytes = 0;       // the arena's size
 };
 
 extern "C" {
@@ -318,6 +319,7 @@ dc_status dc_graph_create(dc_tree t, const dc_kernel_args* a, const dc_tune* tun
   DC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   dc_graph g = new dc_graph_s();
   g->tree = t;
+  g->bytes = p->arena_bytes;
   auto cleanup = [&](dc_status st) {
     if (cs) (void)hipStreamDestroy(cs);
     dc_graph_destroy(g);
@@ -368,6 +370,14 @@ dc_status dc_graph_launch(dc_graph g, void* stream) {
   // back (outside the graph) before the replay reads it
   if (g->tile_T && g->tree->tile_T != g->tile_T) DC_TRY(tree_ensure_tiles(g->tree, g->tile_T, (hipStream_t)stream));
   DC_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return DC_OK;
+}
+
+dc_status dc_graph_image(dc_graph g, const void** host, uint64_t* bytes) {
+  if (!g || !host || !bytes) return fail(DC_E_INVAL, "dc_graph_image: null argument");
+  if (!g->down) return fail(DC_E_STATE, "dc_graph_image: the graph was captured without download");
+  *host = g->down;
+  *bytes = g->bytes;
   return DC_OK;
 }
 

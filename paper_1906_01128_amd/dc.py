@@ -146,6 +146,7 @@ _SIGS = {
     "dc_graph_create": [vp, ctypes.POINTER(KernelArgs), ctypes.POINTER(Tune), u32, ctypes.c_int, ctypes.c_int,
                         ctypes.POINTER(vp)],
     "dc_graph_launch": [vp, vp],
+    "dc_graph_image": [vp, ctypes.POINTER(vp), ctypes.POINTER(u64)],
     "dc_graph_destroy": [vp],
     "dc_server_create": [vp, vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)],
     "dc_server_submit": [vp, ctypes.POINTER(Request), ctypes.POINTER(u64)],
@@ -541,6 +542,15 @@ class Graph:
 
     def launch(self, stream=None):
         _check(load().dc_graph_launch(self.h, _stream_ptr(stream)), "dc_graph_launch")
+
+    def image(self) -> np.ndarray:
+        """A copy of the arena as the last replay brought it back (a graph
+        captured with download=True; synchronize with the replay's stream first)."""
+        host, n = vp(), u64()
+        _check(load().dc_graph_image(self.h, ctypes.byref(host), ctypes.byref(n)), "dc_graph_image")
+        if n.value == 0:
+            return np.zeros(0, np.uint8)
+        return np.frombuffer((ctypes.c_uint8 * n.value).from_address(host.value), np.uint8).copy()
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:

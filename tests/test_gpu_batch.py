@@ -212,6 +212,37 @@ def test_graph_with_upload_restarts_from_image(ctx):
     g.close()
 
 
+@pytest.mark.parametrize("nsims", [30, 500])
+@pytest.mark.parametrize("tune", [dict(tile_chunks=1024, launches=3),
+                                  dict(block=256, wg_per_cu=8, tile_chunks=1024, launches=4)],
+                         ids=["fused", "persistent"])
+def test_graph_whole_job_in_and_out(ctx, nsims, tune):
+    """The whole job in one graph: the staged image in, attach + pass +
+    detach, the arena out (Algorithm 2's transfer, kernel, transfer back).
+    Every replay restarts from the staged image, so the image brought back
+    and the device arena are, each time, the staged image with every leaf
+    advanced one pass by the oracle."""
+    from paper_1906_01128_amd import dc
+    fx.set_threads(0)
+    t = fx.md(seed=41, nsims=nsims)
+    c = Copy(ctx, t, relocate=False)
+    print(f"[gpu] whole-job graph: {c.plan.arena_bytes} B {tune}", flush=True)
+    want = _staged_after_kernel(c, 1)
+    g = c.tree.graph(a=1.0001, b=0.5, tune=tune, upload=True, download=True)
+    for r in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        assert_same_bytes(g.image(), want, f"image brought back, replay {r}")
+        assert_same_bytes(c.device_arena(), want, f"device arena, replay {r}")
+    c.tree.check()
+    g.close()
+    g2 = c.tree.graph(a=1.0001, b=0.5, tune=tune)
+    with pytest.raises(dc.DcError) as e:
+        g2.image()
+    assert e.value.name == "STATE"
+    g2.close()
+
+
 def test_autotune_then_parity(ctx, tmp_path, monkeypatch):
     monkeypatch.setenv("DC_TUNE_CACHE", str(tmp_path / "tune.json"))
     t = fx.md(seed=8, nsims=200, cells_lo=4, cells_hi=64, mean_atoms=16)
