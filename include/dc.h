@@ -458,7 +458,8 @@ enum { DC_BATCH_ATTACH = 1, DC_BATCH_DETACH = 2, DC_BATCH_FORCE_WAIT_BOUND = 4 }
  * wg_per_cu workgroups per compute unit that take them from eight interleaved
  * device queues (reset by a one-workgroup kernel before the launch). ATTACH
  * requires a staged (unrelocated) tree; DETACH leaves it staged again. tune
- * NULL: the cached autotuner choice or defaults. Asynchronous on `stream`.
+ * NULL: the cached autotuner choice, else the fused launch (3) over 1024-chunk
+ * tiles. Asynchronous on `stream`.
  * Runs on one tree must not overlap on different streams: they share its
  * arena and, in the persistent forms, its work queues in the device header. */
 dc_status dc_batch_run(dc_tree tree, const dc_kernel_args* args, const dc_tune* tune, uint32_t flags, void* stream);
