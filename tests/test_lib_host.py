@@ -89,6 +89,24 @@ def test_plan_matches_oracle_workloads():
     _compare(fx.broom(seed=3, bytes_hi=1 << 16))
 
 
+def test_leaf_prefix_table_lies_in_scratch():
+    """The table the deep copy fills on the device (one word per leaf and a
+    total) sits 8-byte aligned inside the scratch buffer the plan asks for,
+    and the leaf count is that of the oracle's layout (FP32/FP64 arrays with
+    at least one element)."""
+    for t in (fx.linear(k=3, n=0), fx.plain(), fx.wide(f1=8, f2=300, lo=1, hi=300), fx.md(nsims=40),
+              fx.random_tree(11, max_objects=4000, nroots=300)):
+        p = plan_of(t)
+        info = p.info()
+        ref = orc.OracleCopy(t.types, t.root_type, t.roots, 64, 1 << 40)
+        objs = ref.objects()
+        leaves = int((((objs["kind"] == 1) | (objs["kind"] == 2)) & (objs["count"] > 0)).sum())
+        assert info.nleaves == leaves
+        assert info.leaf_prefix_offset % 8 == 0
+        assert info.leaf_prefix_offset + 8 * (info.nleaves + 1) <= info.scratch_bytes
+        ref.free()
+
+
 def test_plan_segments_cover_many_targets():
     # more targets than one relocation unit holds, and a struct array with
     # more slots than a unit takes
