@@ -774,7 +774,10 @@ def _batched_secondary(args, torch, dc, ctx, t, plan, tree, info, table):
     tree.detach()
     kd_bytes = 40 * (info.leaf_bytes // 24)    # per double of x: read x, v, f; write x, v
     kd_gbps = kd_bytes / pct(kd, 50) / 1e9
-    whole = _whole_job_graph(torch, tree, plan, info, table)
+    try:
+        whole = _whole_job_graph(torch, tree, plan, info, table)
+    except dc.DcError as e:   # two page-locked buffers of the arena's size: reported, not fatal to the line
+        whole = {"error": str(e)}
     plain = _batched_vs_plain(torch, dc, ctx, t, None, nsub=500)
     return {"forms": best, "whole_job_graph": whole,
             "relocation": {"kernel": "k_relocate", "attach_us": round(1e6 * att_s, 1), "detach_us": round(1e6 * det_s, 1),
