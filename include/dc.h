@@ -139,9 +139,10 @@ typedef struct {
 /* ---- lifecycle --------------------------------------------------------------- */
 
 /* A context on HIP device `device`: owns pinned host staging buffers (eight
- * of 32 MiB, 256 MiB in all, allocated here and freed by dc_ctx_destroy) and
- * a pool of host threads for packing. Errors: DC_E_NOMEM if the pinned
- * staging cannot be allocated, DC_E_HIP. */
+ * of 32 MiB, 256 MiB in all, allocated and written once here, so that no
+ * deep copy pays the first touch of their pages, and freed by
+ * dc_ctx_destroy) and a pool of host threads for packing. Errors:
+ * DC_E_NOMEM if the pinned staging cannot be allocated, DC_E_HIP. */
 dc_status dc_ctx_create(int device, dc_ctx* out);
 /* Frees the context's staging and threads, after every tree, plan and server
  * made with it has been released. Errors: DC_E_INVAL for NULL. */
