@@ -152,12 +152,15 @@ def test_fused_forms_on_small_trees(ctx, name, tune):
     c.tree.check()
 
 
-def test_batch_wide_and_out_of_place(ctx):
+@pytest.mark.parametrize("tune", [None, dict(tile_chunks=1024, launches=1),
+                                  dict(block=256, wg_per_cu=4, tile_chunks=512, launches=4)],
+                         ids=["default", "three", "persistent"])
+def test_batch_wide_and_out_of_place(ctx, tune):
     t = fx.wide(seed=81, f1=16, f2=16, lo=1, hi=5000)
     c = Copy(ctx, t, relocate=False)
     n = c.plan.info().out_bytes
     out = torch.zeros(n, dtype=torch.uint8, device="cuda")
-    c.tree.batch_run(a=0.9999, b=-0.25, attach=True, detach=False, out=out)
+    c.tree.batch_run(a=0.9999, b=-0.25, attach=True, detach=False, out=out, tune=tune)
     want = np.zeros(n, np.uint8)
     c.oracle.run_kernel(0.9999, -0.25, iters=1, select="all", out=want)
     torch.cuda.synchronize()
